@@ -1,0 +1,207 @@
+/*
+ * hisq.h - C ABI of the MI355X (gfx950) HISQ even/odd Dslash and solver library.
+ *
+ * The library applies the HISQ staggered operator (fat one-link plus Naik
+ * three-link SU(3) stencil; the paper's D-slash, Sec. 3, whose application it
+ * names the most performance-critical kernel of its CG, the solver that takes
+ * about 60% of the RHMC time) and solves the even/odd-preconditioned normal
+ * equations (D^+ D + 4 m^2) x = b with the CG variants the paper lists in
+ * Sec. 2: multi-RHS, multi-shift and mixed precision.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice: extents dims[4] = {Lx, Ly, Lz, Lt}, each even and >= 4, volume
+ *   V = Lx*Ly*Lz*Lt < 2^31, Vh = V/2.  Site x = (x0,x1,x2,x3), direction mu =
+ *   0..3 <-> x,y,z,t, parity (x0+x1+x2+x3) & 1 (0 = even).
+ * Checkerboard index of a site: h = lex >> 1 with lex = x0 + Lx*(x1 + Ly*(x2 +
+ *   Lz*x3)).  h runs over [0, Vh) for either parity.
+ * Operator (phases and boundary signs already folded into the links):
+ *   (D chi)(x) = sum_mu [ F_mu(x) chi(x+mu) - F_mu(x-mu)^+ chi(x-mu)
+ *                       + L_mu(x) chi(x+3mu) - L_mu(x-3mu)^+ chi(x-3mu) ]
+ *   D maps one parity to the other.  Normal operator on even sites:
+ *   A = 4 m^2 - D_eo D_oe  ( = (D^+ D + 4 m^2) restricted to even sites, HPD).
+ *
+ * Spinor (colour-vector) buffers, one parity, "[3][Vh]" = colour-major planes:
+ *   HISQ_PREC_FP64  : complex double (re,im interleaved) [3][Vh]     48*Vh bytes
+ *   HISQ_PREC_FP32  : complex float                      [3][Vh]     24*Vh bytes
+ *   HISQ_PREC_FP16S : complex half [3][Vh] (12*Vh bytes) followed by
+ *                     float scale[Vh]; value = scale[h] * half      16*Vh bytes
+ *                     (scale = max |re|,|im| over the site's 6 reals).
+ *   nrhs buffers are stacked back to back: [nrhs][3][Vh].
+ *   hisq_spinor_bytes() returns the size of one such buffer.
+ *
+ * Memory and streams: every data pointer is a DEVICE pointer on the current
+ * HIP device unless stated otherwise.  The caller owns its buffers; the library
+ * never frees them and keeps no reference after a call returns.  A gauge handle
+ * owns the library's own packed link copies and solver workspaces.  `stream`
+ * is a hipStream_t (NULL = the default stream).  Dslash calls are asynchronous
+ * on that stream; solvers order themselves after prior work on it and return
+ * when x is written (synchronous).
+ *
+ * Errors: 0 = OK.  Negative = hard error (nothing usable was written):
+ *   -1 invalid argument, -2 HIP runtime error, -3 out of device memory,
+ *   -4 unsupported.  Positive = soft solver outcome, x and stats valid:
+ *   1 not converged within max_iter, 2 breakdown (non-finite or non-positive
+ *   curvature), 3 converged only after falling back to plain FP64 CG.
+ *   hisq_last_error() returns a message for the calling thread's last failure.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HISQ_OK 0
+#define HISQ_ERR_INVALID -1
+#define HISQ_ERR_HIP -2
+#define HISQ_ERR_OOM -3
+#define HISQ_ERR_UNSUPPORTED -4
+#define HISQ_NOT_CONVERGED 1
+#define HISQ_BREAKDOWN 2
+#define HISQ_CONVERGED_AFTER_FALLBACK 3
+
+#define HISQ_PREC_FP64 0
+#define HISQ_PREC_FP32 1
+#define HISQ_PREC_FP16S 2
+
+/* Bit masks for hisq_gauge_create's prec_mask. */
+#define HISQ_PREC_MASK(p) (1u << (p))
+#define HISQ_PREC_MASK_ALL 7u
+
+typedef struct hisq_gauge_s *hisq_gauge_t;
+typedef struct hisq_nn_s *hisq_nn_t;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int hisq_version(void);
+
+/* Message describing the calling thread's most recent error ("" if none). */
+const char *hisq_last_error(void);
+
+/* Bytes of one spinor buffer of precision `prec` on a lattice with Vh
+ * half-lattice sites, in the layout described above; 0 for a bad prec. */
+size_t hisq_spinor_bytes(int prec, int64_t vh);
+
+/*
+ * Create a gauge handle: validate dims and pack the fat and Naik links into
+ * the library's per-output-site layout for every precision in prec_mask.
+ *   dims     host int[4], extents as above
+ *   fat, lng device, complex double [V][4][3][3] (row a, column b of
+ *            U_mu(x) at ((lex*4 + mu)*3 + a)*3 + b), phases and boundary
+ *            signs folded in.  Only read during the call.
+ *   prec_mask which packed copies to build (HISQ_PREC_MASK bits).  FP16
+ *            links need every entry below 2^14 in magnitude.
+ * On success *out receives the handle.  Errors: -1 bad dims / null pointers /
+ * empty mask, -3 out of memory, -2 HIP failure.
+ */
+int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
+                      unsigned prec_mask, void *stream);
+
+/* Release the handle and everything it owns (NULL is accepted). */
+int hisq_gauge_destroy(hisq_gauge_t g);
+
+/* Bytes of device memory owned by the handle (packed links plus workspaces). */
+int hisq_gauge_device_bytes(hisq_gauge_t g, size_t *bytes);
+
+/*
+ * Single-parity Dslash (the paper's D-slash application, Sec. 3):
+ *   out = D_{pi, 1-pi} in, pi = out_parity (0 even, 1 odd).
+ *   in   spinor of parity 1-pi, out spinor of parity pi, both of `prec`
+ *        (FP16S in and out; arithmetic in FP32 for FP32/FP16S, FP64 for FP64).
+ *   in and out must not overlap.  Asynchronous on `stream`.
+ * Errors: -1 bad parity/prec/pointers, -4 precision not packed in the handle.
+ */
+int hisq_dslash_eo(hisq_gauge_t g, int out_parity, int prec, const void *in, void *out,
+                   void *stream);
+
+/*
+ * Multi-RHS Dslash (the paper's multi-RHS D-slash, Sec. 3: each link load is
+ * applied to several right-hand sides):
+ *   out_i = D in_i                          (diag == NULL)
+ *   out_i = diag[i] * y_i - D in_i          (diag != NULL; diag is a HOST
+ *                                            double[nrhs], y device spinors)
+ * for i = 0..nrhs-1, buffers stacked [nrhs][spinor].  With
+ * diag[i] = 4 m^2 + sigma_i and y = the even vectors that in = D_oe y was
+ * formed from, this is (A + sigma_i) y_i.  For FP16S the epilogue output is
+ * written as FP16S too.  The RHS tile and block shape come from the
+ * autotuner's table (defaults if the shape was never tuned).
+ * Errors: -1 bad arguments (nrhs < 1, y without diag), -4 precision not packed.
+ */
+int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in,
+                          void *out, const double *diag, const void *y, void *stream);
+
+/* Solver controls (host struct).  Zero-initialise and set what you need;
+ * hisq_solver_params_default() fills the defaults noted below. */
+typedef struct {
+    double tol;        /* target true relative residual |b - A x| / |b| (1e-10) */
+    int max_iter;      /* iteration cap per right-hand side (100000) */
+    int sloppy_prec;   /* HISQ_PREC_FP64: plain CG; FP32 / FP16S: mixed precision
+                          with FP64 reliable updates (FP64) */
+    int ru_period;     /* iterations between reliable updates (100) */
+    int graph_chunk;   /* iterations per replay of a captured hipGraph; 0 = eager
+                          kernel launches (32) */
+    int warm_start;    /* nonzero: x holds the initial guess on entry (0) */
+    int fallback;      /* nonzero: after a breakdown or stagnation of a mixed or
+                          preconditioned solve, finish with plain FP64 CG (1) */
+    hisq_nn_t precond; /* NULL, or a network: flexible CG with z = N(r) (NULL) */
+} hisq_solver_params;
+
+/* Per right-hand side (or per shift) solver report. */
+typedef struct {
+    int status;            /* 0 / HISQ_NOT_CONVERGED / HISQ_BREAKDOWN / ..._AFTER_FALLBACK */
+    int iterations;        /* operator applications in the Krylov loop */
+    int reliable_updates;  /* FP64 residual recomputations */
+    int fallback_used;     /* 1 if plain FP64 CG finished the solve */
+    double true_residual;  /* final |b - A x| / |b| computed in FP64 */
+    double wall_ms;        /* wall time of the whole call */
+    double dslash_bytes;   /* algorithmic bytes moved by Dslash launches */
+} hisq_solver_stats;
+
+void hisq_solver_params_default(hisq_solver_params *p);
+
+/*
+ * CG solve of (D^+ D + 4 m^2)_ee x_i = b_i for i = 0..nrhs-1 (the paper's CG,
+ * Sec. 2-3, with its multi-RHS and mixed-precision forms).
+ *   mass  m > 0
+ *   b, x  device, FP64 spinors [nrhs][3][Vh] (even sites); x is overwritten
+ *         with the solution (and read as the initial guess if warm_start).
+ *   p     host params (NULL = defaults); st host array of nrhs stats (or NULL).
+ * nrhs > 1 runs nrhs independent CGs in lockstep sharing multi-RHS Dslash
+ * launches.  Stops on the FP64 true residual.  Synchronous.
+ * Returns the worst per-RHS status (0 if all converged).
+ */
+int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double *x,
+                  const hisq_solver_params *p, hisq_solver_stats *st, void *stream);
+
+/*
+ * Multi-shift CG (the paper's multiple-shift CG, Sec. 2): (A + sigma_k) x_k = b
+ * for k = 0..nshift-1 from one Krylov space, each shift stopped on its own
+ * residual, then every shift checked (and if needed refined by CG) on its
+ * FP64 true residual.
+ *   shifts host double[nshift], every sigma_k + 4 m^2 > 0
+ *   b      device FP64 spinor [3][Vh];  x device FP64 [nshift][3][Vh]
+ *   st     host array of nshift stats (or NULL)
+ */
+int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *shifts,
+                       const double *b, double *x, const hisq_solver_params *p,
+                       hisq_solver_stats *st, void *stream);
+
+/*
+ * Gauge-covariant preconditioner network, z = N(r): a stack of linear layers
+ * psi'_a(x) = sum_b [ W0_ab psi_b(x) + sum_mu ( Wf_mu,ab U_mu(x) psi_b(x+mu)
+ *                                            + Wb_mu,ab U_mu(x-mu)^+ psi_b(x-mu) ) ]
+ * on the full lattice (the even input embedded with zeros on odd sites, the
+ * output projected back to even sites), channel counts 1 -> C -> ... -> 1.
+ *   in, out  device FP32 spinors [3][Vh] (even parity)
+ * Errors: -1 bad arguments, -4 the handle was created without thin links.
+ */
+int hisq_precond_apply(hisq_gauge_t g, hisq_nn_t net, const void *in, void *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISQ_H */

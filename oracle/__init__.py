@@ -20,6 +20,7 @@ Parts:
 from .core import (  # noqa: F401
     dslash,
     dslash_phased,
+    dslash_sites,
     normal_op,
     cg,
     multishift_cg,

@@ -37,6 +37,7 @@ def _lib():
                                   ip, dp]
         lib.oracle_cg.restype = C.c_int
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_dslash_sites.argtypes = [ip, dp, dp, dp, C.POINTER(C.c_int64), C.c_long, dp]
         _LIB = lib
     return _LIB
 
@@ -76,6 +77,16 @@ def dslash(dims, fat, lng, vec, out_parity: int) -> np.ndarray:
     fat, lng, vec = _links(dims, fat), _links(dims, lng), _vec(dims, vec)
     out = np.empty_like(vec)
     _lib().oracle_dslash(_dims(dims), _ptr(fat), _ptr(lng), _ptr(vec), _ptr(out), int(out_parity))
+    return out
+
+
+def dslash_sites(dims, fat, lng, vec, sites) -> np.ndarray:
+    """(D vec) at the given lexicographic sites only; returns [len(sites), 3]."""
+    fat, lng, vec = _links(dims, fat), _links(dims, lng), _vec(dims, vec)
+    sites = np.ascontiguousarray(sites, np.int64)
+    out = np.empty((len(sites), 3), np.complex128)
+    _lib().oracle_dslash_sites(_dims(dims), _ptr(fat), _ptr(lng), _ptr(vec),
+                               sites.ctypes.data_as(C.POINTER(C.c_int64)), len(sites), _ptr(out))
     return out
 
 

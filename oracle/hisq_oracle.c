@@ -106,6 +106,28 @@ void oracle_dslash(const int L[4], const double *fat_, const double *lng_,
     }
 }
 
+/* The same sum evaluated only at the listed sites (any parity): out[i][3] =
+ * (D in)(sites[i]).  Lets a huge lattice be checked at sampled outputs. */
+void oracle_dslash_sites(const int L[4], const double *fat_, const double *lng_, const double *in_,
+                         const int64_t *sites, long nsites, double *out_) {
+    const cplx *F = (const cplx *)fat_, *N = (const cplx *)lng_, *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nsites; ++i) {
+        const long s = (long)sites[i];
+        cplx acc[3] = {0, 0, 0};
+        for (int mu = 0; mu < 4; ++mu) {
+            long f1 = neighbour(L, s, mu, +1), b1 = neighbour(L, s, mu, -1);
+            long f3 = neighbour(L, s, mu, +3), b3 = neighbour(L, s, mu, -3);
+            add_mv(acc, link_at(F, s, mu), in + f1 * 3, +1.0);
+            add_mdag_v(acc, link_at(F, b1, mu), in + b1 * 3, -1.0);
+            add_mv(acc, link_at(N, s, mu), in + f3 * 3, +1.0);
+            add_mdag_v(acc, link_at(N, b3, mu), in + b3 * 3, -1.0);
+        }
+        for (int a = 0; a < 3; ++a) out[i * 3 + a] = acc[a];
+    }
+}
+
 /* Staggered phase eta_mu(x): 1, (-1)^x, (-1)^(x+y), (-1)^(x+y+z). */
 static double eta_of(const int c[4], int mu) {
     int e = 0;

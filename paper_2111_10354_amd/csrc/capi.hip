@@ -1,0 +1,248 @@
+// C ABI of the library: argument validation, handle life cycle, error codes.
+// Every entry point validates its arguments on the host before touching the
+// GPU; invalid arguments return HISQ_ERR_INVALID without any HIP call.
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "solver_internal.h"
+
+namespace hisq {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *get_error() { return g_last_error.c_str(); }
+
+static int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+static bool valid_prec(int p) { return p == HISQ_PREC_FP64 || p == HISQ_PREC_FP32 || p == HISQ_PREC_FP16S; }
+
+static int check_dims(const int *dims) {
+    if (!dims) return fail(HISQ_ERR_INVALID, "dims is NULL");
+    int64_t v = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (dims[i] < 4 || (dims[i] & 1))
+            return fail(HISQ_ERR_INVALID, "every lattice extent must be even and >= 4");
+        v *= dims[i];
+    }
+    if (v >= ((int64_t)1 << 31)) return fail(HISQ_ERR_INVALID, "lattice volume must be below 2^31");
+    return HISQ_OK;
+}
+
+static int check_handle(hisq_gauge_t g) {
+    if (!g) return fail(HISQ_ERR_INVALID, "gauge handle is NULL");
+    return HISQ_OK;
+}
+
+static int check_params(const hisq_solver_params &p) {
+    if (!(p.tol > 0.0) || !std::isfinite(p.tol)) return fail(HISQ_ERR_INVALID, "tol must be positive");
+    if (p.max_iter < 1) return fail(HISQ_ERR_INVALID, "max_iter must be >= 1");
+    if (!valid_prec(p.sloppy_prec)) return fail(HISQ_ERR_INVALID, "bad sloppy_prec");
+    if (p.graph_chunk < 0 || p.graph_chunk > 4096) return fail(HISQ_ERR_INVALID, "graph_chunk out of range");
+    if (p.precond) return fail(HISQ_ERR_UNSUPPORTED, "preconditioned CG is not available in this build");
+    return HISQ_OK;
+}
+
+}  // namespace hisq
+
+using namespace hisq;
+
+hisq_gauge_s::~hisq_gauge_s() {
+    cg_ws.clear();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+}
+
+extern "C" {
+
+int hisq_version(void) { return 100; }
+
+const char *hisq_last_error(void) { return get_error(); }
+
+size_t hisq_spinor_bytes(int prec, int64_t vh) {
+    if (!valid_prec(prec) || vh < 0) return 0;
+    return spinor_bytes(prec, vh);
+}
+
+void hisq_solver_params_default(hisq_solver_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->tol = 1e-10;
+    p->max_iter = 100000;
+    p->sloppy_prec = HISQ_PREC_FP64;
+    p->ru_period = 100;
+    p->graph_chunk = 32;
+    p->warm_start = 0;
+    p->fallback = 1;
+    p->precond = nullptr;
+}
+
+int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
+                      unsigned prec_mask, void *stream) {
+    if (!out) return fail(HISQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!fat || !lng) return fail(HISQ_ERR_INVALID, "fat and long link pointers are required");
+    if (prec_mask == 0 || (prec_mask & ~HISQ_PREC_MASK_ALL))
+        return fail(HISQ_ERR_INVALID, "prec_mask must be a nonzero combination of HISQ_PREC_MASK bits");
+    hipStream_t s = (hipStream_t)stream;
+    hisq_gauge_s *g = new (std::nothrow) hisq_gauge_s();
+    if (!g) return fail(HISQ_ERR_OOM, "host allocation failed");
+    std::memcpy(g->dims, dims, sizeof(g->dims));
+    g->geom = make_geom(dims);
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(HISQ_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    DevBuf maxabs;
+    if ((rc = maxabs.alloc(sizeof(float)))) {
+        delete g;
+        return rc;
+    }
+    for (int f = 0; f < 3; ++f) {
+        if (!(prec_mask & HISQ_PREC_MASK(f))) continue;
+        const size_t bytes = link_parity_bytes(f, g->geom.vh);
+        if ((rc = g->links[f][0].alloc(bytes)) || (rc = g->links[f][1].alloc(bytes))) {
+            delete g;
+            return rc;
+        }
+        float *mb = nullptr;
+        if (f == H16) {
+            e = hipMemsetAsync(maxabs.p, 0, sizeof(float), s);
+            mb = (float *)maxabs.p;
+        }
+        if (e == hipSuccess)
+            rc = launch_pack_links(g->geom, f, fat, lng, g->links[f][0].p, g->links[f][1].p, mb, s);
+        if (e != hipSuccess || rc) {
+            delete g;
+            return rc ? rc : fail(HISQ_ERR_HIP, hipGetErrorString(e));
+        }
+        if (f == H16) {
+            float m = 0.f;
+            e = hipMemcpyAsync(&m, maxabs.p, sizeof(float), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                delete g;
+                return fail(HISQ_ERR_HIP, hipGetErrorString(e));
+            }
+            if (!(m < 16384.f)) {
+                delete g;
+                return fail(HISQ_ERR_INVALID, "link entries too large (or non-finite) for FP16 storage");
+            }
+        }
+    }
+    e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(HISQ_ERR_HIP, std::string("create: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return HISQ_OK;
+}
+
+int hisq_gauge_destroy(hisq_gauge_t g) {
+    if (!g) return HISQ_OK;
+    (void)hipDeviceSynchronize();
+    delete g;
+    return HISQ_OK;
+}
+
+int hisq_gauge_device_bytes(hisq_gauge_t g, size_t *bytes) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (!bytes) return fail(HISQ_ERR_INVALID, "bytes is NULL");
+    size_t n = g->diag_buf.bytes;
+    for (auto &f : g->links)
+        for (auto &b : f) n += b.bytes;
+    *bytes = n;
+    return HISQ_OK;
+}
+
+int hisq_dslash_eo(hisq_gauge_t g, int out_parity, int prec, const void *in, void *out, void *stream) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (out_parity != 0 && out_parity != 1) return fail(HISQ_ERR_INVALID, "out_parity must be 0 or 1");
+    if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
+    if (!in || !out) return fail(HISQ_ERR_INVALID, "in and out are required");
+    if (in == out) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
+    return gauge_dslash(g, out_parity, prec, prec, prec, 1, in, out, nullptr, nullptr, nullptr, nullptr,
+                        (hipStream_t)stream);
+}
+
+int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in, void *out,
+                          const double *diag, const void *y, void *stream) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (out_parity != 0 && out_parity != 1) return fail(HISQ_ERR_INVALID, "out_parity must be 0 or 1");
+    if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
+    if (nrhs < 1) return fail(HISQ_ERR_INVALID, "nrhs must be >= 1");
+    if (!in || !out) return fail(HISQ_ERR_INVALID, "in and out are required");
+    if (in == out) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
+    if ((diag == nullptr) != (y == nullptr)) return fail(HISQ_ERR_INVALID, "diag and y go together");
+    hipStream_t s = (hipStream_t)stream;
+    const double *ddev = nullptr;
+    double *part = nullptr;
+    if (diag) {
+        for (int i = 0; i < nrhs; ++i)
+            if (!std::isfinite(diag[i])) return fail(HISQ_ERR_INVALID, "diag must be finite");
+        std::lock_guard<std::mutex> lk(g->mu);
+        const size_t need = sizeof(double) * nrhs + sizeof(double) * (size_t)nrhs * ((g->geom.vh + 63) / 64);
+        if ((rc = g->diag_buf.alloc(need))) return rc;
+        HISQ_HIP_CHECK(hipMemcpyAsync(g->diag_buf.p, diag, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+        ddev = (const double *)g->diag_buf.p;
+        part = (double *)g->diag_buf.p + nrhs;
+    }
+    return gauge_dslash(g, out_parity, prec, prec, prec, nrhs, in, out, y, ddev, part, nullptr, s);
+}
+
+int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double *x,
+                  const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    hisq_solver_params prm;
+    if (p) prm = *p;
+    else hisq_solver_params_default(&prm);
+    if ((rc = check_params(prm))) return rc;
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
+    if (nrhs < 1) return fail(HISQ_ERR_INVALID, "nrhs must be >= 1");
+    if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
+    if (b == x) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
+    std::lock_guard<std::mutex> lk(g->mu);
+    return cg_solve(g, mass, nrhs, b, x, nullptr, prm, st, (hipStream_t)stream);
+}
+
+int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *shifts, const double *b,
+                       double *x, const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    hisq_solver_params prm;
+    if (p) prm = *p;
+    else hisq_solver_params_default(&prm);
+    if ((rc = check_params(prm))) return rc;
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
+    if (nshift < 1 || nshift > 256 || !shifts)
+        return fail(HISQ_ERR_INVALID, "1 <= nshift <= 256 and shifts are required");
+    for (int k = 0; k < nshift; ++k)
+        if (!std::isfinite(shifts[k]) || !(shifts[k] + 4.0 * mass * mass > 0.0))
+            return fail(HISQ_ERR_INVALID, "every shift must be finite with sigma + 4 m^2 > 0");
+    if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
+    std::lock_guard<std::mutex> lk(g->mu);
+    return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
+}
+
+int hisq_precond_apply(hisq_gauge_t g, hisq_nn_t net, const void *in, void *out, void *stream) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (!net || !in || !out) return fail(HISQ_ERR_INVALID, "net, in and out are required");
+    (void)stream;
+    return fail(HISQ_ERR_UNSUPPORTED, "the preconditioner network is not available in this build");
+}
+
+}  // extern "C"

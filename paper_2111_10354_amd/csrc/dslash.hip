@@ -1,0 +1,211 @@
+// HISQ single-parity Dslash for gfx950, single- and multi-RHS.
+//
+// One thread owns one output site h and a tile of TILE right-hand sides.  For
+// each of the 16 link slots it streams the 9 complex entries of the slot's
+// link once (non-temporal: each link is read exactly once per application and
+// must not evict the spinors that neighbouring sites still reuse), gathers the
+// neighbour colour vector of every RHS in the tile and accumulates the 3x3
+// complex mat-vec.  All 16 slots are laid out per output site, so every link
+// load of a wavefront is one contiguous plane segment; the neighbour gathers
+// of a wavefront touch a contiguous run of sites shifted by the hop.
+//
+// Epilogue (optional): out_i = diag_i * y_i - (D in)_i and a per-block FP64
+// partial of Re <y_i, out_i>, which is what CG needs for <p, A p>.
+//
+// The stencil is a 3x3 complex mat-vec per hop: 1146 flop per site against
+// 1200 bytes (FP32), far below the ridge point, so it is written for memory
+// throughput on the vector ALUs; matrix cores would gain nothing here.
+
+#include "solver_internal.h"
+
+namespace hisq {
+
+Geom make_geom(const int dims[4]) {
+    Geom g;
+    for (int i = 0; i < 4; ++i) g.L[i] = dims[i];
+    g.lxh = dims[0] / 2;
+    g.vh = (int)((int64_t)dims[0] * dims[1] * dims[2] * dims[3] / 2);
+    g.sy = g.lxh;
+    g.sz = g.lxh * dims[1];
+    g.st = g.lxh * dims[1] * dims[2];
+    return g;
+}
+
+int dslash_grid_blocks(const Geom &g, int block) { return (g.vh + block - 1) / block; }
+
+template <int F>
+struct LinkView;
+template <> struct LinkView<F64> { static Links<F64> make(const void *p, int vh) { return {(const d2v *)p, vh}; } };
+template <> struct LinkView<F32> { static Links<F32> make(const void *p, int vh) { return {(const float *)p, vh}; } };
+template <> struct LinkView<H16> {
+    static Links<H16> make(const void *p, int vh) { return {(const unsigned int *)p, vh}; }
+};
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int LF, int SI, int SO, int TILE, bool EPI>
+__global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Spinor<SI> in,
+                                                     Spinor<SO> out, Spinor<SI> y,
+                                                     const double *__restrict__ diag,
+                                                     double *__restrict__ partials,
+                                                     const CgState *__restrict__ skip, int parity,
+                                                     int nrhs) {
+    typedef typename RealOf<LF>::T R;
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int h = blk * blockDim.x + threadIdx.x;
+    const int r0 = blockIdx.y * TILE;
+    if (skip) {
+        bool idle = true;
+#pragma unroll
+        for (int r = 0; r < TILE; ++r)
+            if (r0 + r < nrhs && skip[r0 + r].flag == CG_RUNNING) idle = false;
+        if (idle) return;  // uniform over the block
+    }
+
+    double part[TILE];
+#pragma unroll
+    for (int r = 0; r < TILE; ++r) part[r] = 0.0;
+
+    if (h < g.vh) {
+        const SiteCoord sc = decode_site(g, h, parity);
+        cx<R> acc[TILE][3];
+#pragma unroll
+        for (int r = 0; r < TILE; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[r][c] = {R(0), R(0)};
+
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int nbh = hop_index(g, sc, h, mu, slot_dist(j));
+                cx<R> w[9];
+                links.load(4 * mu + j, h, w);
+#pragma unroll
+                for (int r = 0; r < TILE; ++r) {
+                    if (TILE > 1 && r0 + r >= nrhs) break;
+                    const Spinor<SI> src = in.rhs(r0 + r);
+                    cx<R> v[3];
+                    src.load(nbh, v);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) cmac(acc[r][a], w[3 * a + b], v[b]);
+                }
+            }
+        }
+
+#pragma unroll
+        for (int r = 0; r < TILE; ++r) {
+            if (TILE > 1 && r0 + r >= nrhs) break;
+            cx<R> o[3];
+            if constexpr (EPI) {
+                const Spinor<SI> ys = y.rhs(r0 + r);
+                cx<R> yv[3];
+                ys.load(h, yv);
+                const R d = (R)diag[r0 + r];
+                double pr = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    o[c] = {d * yv[c].re - acc[r][c].re, d * yv[c].im - acc[r][c].im};
+                    pr += (double)yv[c].re * (double)o[c].re + (double)yv[c].im * (double)o[c].im;
+                }
+                part[r] = pr;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o[c] = acc[r][c];
+            }
+            const Spinor<SO> dst = out.rhs(r0 + r);
+            typedef typename RealOf<SO>::T RO;
+            cx<RO> oo[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) oo[c] = {(RO)o[c].re, (RO)o[c].im};
+            dst.store(h, oo);
+        }
+    }
+
+    if constexpr (EPI) {
+        // deterministic block reduction: wave shuffles, then waves in order
+        __shared__ double red[4][TILE];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int r = 0; r < TILE; ++r) {
+            double s = wave_sum(part[r]);
+            if (lane == 0) red[wv][r] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < TILE && r0 + (int)threadIdx.x < nrhs) {
+            const int r = threadIdx.x;
+            double s = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][r];
+            partials[(size_t)(r0 + r) * nb + blk] = s;
+        }
+    }
+}
+
+template <int LF, int SI, int SO, int TILE, bool EPI>
+static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+    dim3 block(a.block);
+    dim3 grid(dslash_grid_blocks(g, a.block), (a.nrhs + TILE - 1) / TILE);
+    Links<LF> L = LinkView<LF>::make(a.links, g.vh);
+    Spinor<SI> in = spinor_view<SI>(const_cast<void *>(a.in), g.vh);
+    Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
+    Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);
+    hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI>), grid, block, 0, s, g, L, in, out, y,
+                       a.diag, a.partials, a.skip, a.parity, a.nrhs);
+}
+
+template <int LF, int SI, int SO, bool EPI>
+static int launch_tile(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+    switch (a.tile) {
+        case 1: launch_one<LF, SI, SO, 1, EPI>(g, a, s); return 0;
+        case 2: launch_one<LF, SI, SO, 2, EPI>(g, a, s); return 0;
+        case 4: launch_one<LF, SI, SO, 4, EPI>(g, a, s); return 0;
+        case 8:
+            if constexpr (LF != F64) {
+                launch_one<LF, SI, SO, 8, EPI>(g, a, s);
+                return 0;
+            }
+            [[fallthrough]];
+        default: return -1;
+    }
+}
+
+template <int LF, int SI, int SO>
+static int launch_epi(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+    return a.diag ? launch_tile<LF, SI, SO, true>(g, a, s) : launch_tile<LF, SI, SO, false>(g, a, s);
+}
+
+int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+    if (a.block != 64 && a.block != 128 && a.block != 256) {
+        set_error("dslash: block size must be 64, 128 or 256");
+        return HISQ_ERR_INVALID;
+    }
+    int rc = -1;
+    if (a.fmt_links == F64 && a.fmt_in == F64 && a.fmt_out == F64)
+        rc = launch_epi<F64, F64, F64>(g, a, s);
+    else if (a.fmt_links == F32 && a.fmt_in == F32 && a.fmt_out == F32)
+        rc = launch_epi<F32, F32, F32>(g, a, s);
+    else if (a.fmt_links == H16 && a.fmt_in == H16 && a.fmt_out == H16)
+        rc = launch_epi<H16, H16, H16>(g, a, s);
+    else if (a.fmt_links == H16 && a.fmt_in == H16 && a.fmt_out == F32)
+        rc = launch_epi<H16, H16, F32>(g, a, s);
+    if (rc != 0) {
+        set_error("dslash: unsupported precision / tile combination");
+        return HISQ_ERR_UNSUPPORTED;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("dslash launch: ") + hipGetErrorString(e));
+        return HISQ_ERR_HIP;
+    }
+    return HISQ_OK;
+}
+
+}  // namespace hisq

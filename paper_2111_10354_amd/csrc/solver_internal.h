@@ -1,0 +1,132 @@
+// Host-side structures of the solver runtime: the gauge handle, per-RHS CG
+// state kept in device memory, workspaces and cached graphs.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "hisq_internal.h"
+
+namespace hisq {
+
+// Life cycle of one right-hand side inside the device-side iteration.
+enum CgFlag {
+    CG_RUNNING = 0,    // iterating
+    CG_ATTENTION = 1,  // reliable update / convergence check / cap reached: host acts
+    CG_DONE = 2,       // true residual below the target
+    CG_BREAKDOWN = 3,  // non-finite value or non-positive curvature
+    CG_MAXITER = 4,    // iteration cap reached without convergence
+    CG_RESUME = 5      // transient: residual replaced, p update pending
+};
+
+struct CgState {
+    double rho;      // <r, r> of the current residual
+    double rho_new;  // <r, r> after the last update
+    double pap;      // Re <p, A p>
+    double alpha, beta;
+    double stop2;    // (tol |b|)^2
+    double true_rr;  // last |b - A x|^2 computed in FP64
+    int iter;        // completed iterations
+    int since_ru;    // iterations since the last reliable update
+    int ru_period;   // 0: no periodic reliable update
+    int max_iter;
+    int flag;
+    int reliable;    // reliable updates done
+};
+
+enum { RED_ALPHA, RED_BETA, RED_TRUE, RED_INIT, RED_STORE };
+
+int blas_blocks(int vh);
+void launch_update_xr(int fmt_sloppy, int vh, int n, void *x, void *r, const void *p, const void *q,
+                      const CgState *st, double *part, hipStream_t s);
+void launch_update_p(int fmt_sloppy, int vh, int n, const void *r, void *p, const CgState *st, int when,
+                     hipStream_t s);
+int launch_convert(int fs, int fd, int vh, int n, const void *src, void *dst, const CgState *st, int when,
+                   hipStream_t s);
+void launch_accum_zero(int fmt_x, int vh, int n, void *xhi, void *xs, const CgState *st, int when,
+                       hipStream_t s);
+void launch_residual(int vh, int n, const void *b, const void *ax, void *r, const CgState *st, int when,
+                     double *part, hipStream_t s);
+void launch_norm2(int vh, int n, const void *v, double *part, hipStream_t s);
+void launch_zero(int fmt, int vh, int n, void *v, hipStream_t s);
+void launch_reduce(int which, int n, const double *part, int nb, CgState *st, double *out, hipStream_t s);
+void launch_resume_flags(int n, CgState *st, hipStream_t s);
+
+// Device allocation owned by the handle.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t n);
+};
+
+// Tuned launch shape of the Dslash for one (precision pair, nrhs).
+struct DslashShape {
+    int tile = 1;
+    int block = 256;
+};
+
+// Buffers, device state and the captured iteration graph of one solver shape.
+struct CgWorkspace {
+    int n = 0, fmt = F64, chunk = 0;
+    DevBuf b64, x64, r64, t64, ax64, p64, q64;
+    DevBuf xs, rs, ps, ts, qs;
+    DevBuf part, state, diag, scal;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~CgWorkspace() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    // sloppy views (aliases of the FP64 buffers in plain mode)
+    void *X() { return fmt == F64 ? x64.p : xs.p; }
+    void *R() { return fmt == F64 ? r64.p : rs.p; }
+    void *P() { return fmt == F64 ? p64.p : ps.p; }
+    void *T() { return fmt == F64 ? t64.p : ts.p; }
+    void *Q() { return fmt == F64 ? q64.p : qs.p; }
+    CgState *st() { return (CgState *)state.p; }
+};
+
+}  // namespace hisq
+
+struct hisq_gauge_s {
+    int dims[4];
+    hisq::Geom geom;
+    int device = 0;
+    hisq::DevBuf links[3][2];  // [format][output parity]
+    hisq::DevBuf diag_buf;     // epilogue coefficients for hisq_dslash_multi_rhs
+    hipStream_t capture_stream = nullptr;
+    std::mutex mu;
+    // autotuned shapes keyed by (links fmt, in fmt, out fmt, nrhs, epilogue)
+    std::map<std::tuple<int, int, int, int, int>, hisq::DslashShape> shapes;
+    std::map<std::tuple<int, int, int>, std::unique_ptr<hisq::CgWorkspace>> cg_ws;  // (n, fmt, chunk)
+    ~hisq_gauge_s();
+};
+
+namespace hisq {
+
+DslashShape pick_shape(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi);
+
+// Dslash on the handle's packed links.
+int gauge_dslash(hisq_gauge_s *g, int out_parity, int fmt_links, int fmt_in, int fmt_out, int nrhs,
+                 const void *in, void *out, const void *y, const double *diag_dev, double *partials,
+                 const CgState *skip, hipStream_t s);
+
+int nb_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int n, bool epi);
+size_t dslash_algorithmic_bytes(int fmt_links, int fmt_in, int fmt_out, int64_t vh, int nrhs, bool epi);
+
+int cg_solve(hisq_gauge_s *g, double mass, int nrhs, const double *b, double *x, const double *sigma,
+             const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);
+
+int multishift_solve(hisq_gauge_s *g, double mass, int nshift, const double *shifts, const double *b,
+                     double *x, const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);
+
+}  // namespace hisq

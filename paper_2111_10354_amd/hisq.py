@@ -1,0 +1,214 @@
+"""Python binding of libhisq.so: argument marshalling only.
+
+Every function here forwards to the C ABI declared in ``include/hisq.h`` with
+the same name; all arithmetic runs in the library's HIP kernels.  Torch tensors
+are used only as device buffers and for the current HIP stream.  If the
+library has not been built, importing this module raises - there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhisq.so")
+
+PREC_FP64, PREC_FP32, PREC_FP16S = 0, 1, 2
+PREC_NAMES = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16s": PREC_FP16S}
+
+OK, ERR_INVALID, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+NOT_CONVERGED, BREAKDOWN, CONVERGED_AFTER_FALLBACK = 1, 2, 3
+
+
+class HisqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hisq error {code}: {msg}")
+        self.code = code
+
+
+class SolverParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("sloppy_prec", C.c_int),
+                ("ru_period", C.c_int), ("graph_chunk", C.c_int), ("warm_start", C.c_int),
+                ("fallback", C.c_int), ("precond", C.c_void_p)]
+
+
+class SolverStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("reliable_updates", C.c_int),
+                ("fallback_used", C.c_int), ("true_residual", C.c_double), ("wall_ms", C.c_double),
+                ("dslash_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2111_10354_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = C.CDLL(LIB_PATH)
+    vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+    sig = {
+        "hisq_version": (C.c_int, []),
+        "hisq_last_error": (C.c_char_p, []),
+        "hisq_spinor_bytes": (C.c_size_t, [C.c_int, C.c_int64]),
+        "hisq_gauge_create": (C.c_int, [C.POINTER(vp), ip, vp, vp, C.c_uint, vp]),
+        "hisq_gauge_destroy": (C.c_int, [vp]),
+        "hisq_gauge_device_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "hisq_dslash_eo": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp]),
+        "hisq_dslash_multi_rhs": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, dp, vp, vp]),
+        "hisq_solver_params_default": (None, [C.POINTER(SolverParams)]),
+        "hisq_cg_solve": (C.c_int, [vp, C.c_double, C.c_int, vp, vp, C.POINTER(SolverParams),
+                                    C.POINTER(SolverStats), vp]),
+        "hisq_multishift_cg": (C.c_int, [vp, C.c_double, C.c_int, dp, vp, vp, C.POINTER(SolverParams),
+                                         C.POINTER(SolverStats), vp]),
+        "hisq_precond_apply": (C.c_int, [vp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+# C ABI entry points declared in include/hisq.h (checked by the test-suite).
+EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_create",
+           "hisq_gauge_destroy", "hisq_gauge_device_bytes", "hisq_dslash_eo", "hisq_dslash_multi_rhs",
+           "hisq_solver_params_default", "hisq_cg_solve", "hisq_multishift_cg", "hisq_precond_apply")
+
+
+def last_error() -> str:
+    return (LIB.hisq_last_error() or b"").decode()
+
+
+def _check(rc: int, allow_soft: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_soft):
+        raise HisqError(rc, last_error())
+    return rc
+
+
+def _prec(p) -> int:
+    return PREC_NAMES[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("device tensors are required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensors are required")
+    return C.c_void_p(t.data_ptr())
+
+
+def version() -> int:
+    return LIB.hisq_version()
+
+
+def spinor_bytes(prec, vh: int) -> int:
+    return int(LIB.hisq_spinor_bytes(_prec(prec), int(vh)))
+
+
+def empty_spinor(prec, vh: int, nrhs: int = 1, device="cuda") -> torch.Tensor:
+    """A raw device buffer of nrhs stacked spinors of the given precision."""
+    return torch.empty(spinor_bytes(prec, vh) * nrhs, dtype=torch.uint8, device=device)
+
+
+class Gauge:
+    """Handle owning the packed link copies (see hisq_gauge_create)."""
+
+    def __init__(self, dims, fat: torch.Tensor, lng: torch.Tensor, precs=("fp64", "fp32", "fp16s"),
+                 stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        V = 1
+        for d in self.dims:
+            V *= d
+        self.vh = V // 2
+        for t in (fat, lng):
+            if t.dtype not in (torch.complex128, torch.float64) or t.numel() * t.element_size() != V * 4 * 9 * 16:
+                raise ValueError("links must be complex128 [V,4,3,3] device tensors")
+        mask = 0
+        for p in precs:
+            mask |= 1 << _prec(p)
+        h = C.c_void_p()
+        d = (C.c_int * 4)(*self.dims)
+        _check(LIB.hisq_gauge_create(C.byref(h), d, _ptr(fat), _ptr(lng), mask, _stream(stream)))
+        self.handle = h
+
+    def device_bytes(self) -> int:
+        n = C.c_size_t()
+        _check(LIB.hisq_gauge_device_bytes(self.handle, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            LIB.hisq_gauge_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gauge_create(dims, fat, lng, precs=("fp64", "fp32", "fp16s"), stream=None) -> Gauge:
+    return Gauge(dims, fat, lng, precs, stream)
+
+
+def dslash_eo(g: Gauge, out_parity: int, prec, inp: torch.Tensor, out: torch.Tensor, stream=None):
+    _check(LIB.hisq_dslash_eo(g.handle, int(out_parity), _prec(prec), _ptr(inp), _ptr(out), _stream(stream)))
+
+
+def dslash_multi_rhs(g: Gauge, out_parity: int, prec, nrhs: int, inp, out, diag=None, y=None, stream=None):
+    dd = None
+    if diag is not None:
+        dd = (C.c_double * nrhs)(*[float(v) for v in diag])
+    _check(LIB.hisq_dslash_multi_rhs(g.handle, int(out_parity), _prec(prec), int(nrhs), _ptr(inp), _ptr(out),
+                                     dd, _ptr(y), _stream(stream)))
+
+
+def solver_params(**kw) -> SolverParams:
+    p = SolverParams()
+    LIB.hisq_solver_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "sloppy_prec":
+            v = _prec(v)
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def cg_solve(g: Gauge, mass: float, nrhs: int, b, x, params: SolverParams | None = None, stream=None):
+    """Returns (status, [stats dict per RHS])."""
+    st = (SolverStats * nrhs)()
+    rc = LIB.hisq_cg_solve(g.handle, float(mass), int(nrhs), _ptr(b), _ptr(x),
+                           C.byref(params) if params is not None else None, st, _stream(stream))
+    _check(rc, allow_soft=True)
+    return rc, [s.as_dict() for s in st]
+
+
+def multishift_cg(g: Gauge, mass: float, shifts, b, x, params: SolverParams | None = None, stream=None):
+    n = len(shifts)
+    sh = (C.c_double * n)(*[float(v) for v in shifts])
+    st = (SolverStats * n)()
+    rc = LIB.hisq_multishift_cg(g.handle, float(mass), n, sh, _ptr(b), _ptr(x),
+                                C.byref(params) if params is not None else None, st, _stream(stream))
+    _check(rc, allow_soft=True)
+    return rc, [s.as_dict() for s in st]
+
+
+def precond_apply(g: Gauge, net, inp, out, stream=None):
+    _check(LIB.hisq_precond_apply(g.handle, net, _ptr(inp), _ptr(out), _stream(stream)))

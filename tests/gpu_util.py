@@ -1,0 +1,50 @@
+"""Shared helpers of the GPU tests: field caches, gauge handles, buffer moves."""
+
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import synth
+
+
+def hisq():
+    from paper_2111_10354_amd import hisq as h
+    return h
+
+
+@functools.lru_cache(maxsize=8)
+def fields(dims, cfg_id=99, eps=0.5, apbc=False, free=None):
+    if free is not None:
+        return synth.free_links(dims, free[0], free[1], antiperiodic_t=apbc)
+    return synth.hisq_links(dims, cfg_id, eps, antiperiodic_t=apbc)
+
+
+def device_links(F, L):
+    import torch
+    return torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
+
+
+def make_gauge(dims, F, L, precs=("fp64", "fp32", "fp16s")):
+    import torch
+    f, l = device_links(F, L)
+    g = hisq().Gauge(dims, f, l, precs)
+    torch.cuda.synchronize()
+    del f, l
+    return g
+
+
+def to_device(raw: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(raw)).cuda()
+
+
+def to_host(t) -> np.ndarray:
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def flush(msg: str):
+    print(msg, flush=True)

@@ -1,0 +1,109 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/hisq.h declares, and rejects bad arguments before touching the GPU."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hisq.h")
+LIB = os.path.join(ROOT, "paper_2111_10354_amd", "libhisq.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hisq_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libhisq.so is not built (run __graft_entry__.build())")
+    return C.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "hisq_dslash_eo" in names and "hisq_cg_solve" in names
+    for required in ("hisq_dslash_eo", "hisq_dslash_multi_rhs", "hisq_cg_solve", "hisq_multishift_cg",
+                     "hisq_precond_apply"):
+        assert required in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_export():
+    from paper_2111_10354_amd import hisq
+    assert set(hisq.EXPORTS) == set(declared_functions())
+    for n in declared_functions():
+        assert hasattr(hisq.LIB, n)
+
+
+def test_spinor_bytes(lib):
+    f = lib.hisq_spinor_bytes
+    f.restype = C.c_size_t
+    f.argtypes = [C.c_int, C.c_int64]
+    assert f(0, 10) == 480 and f(1, 10) == 240 and f(2, 10) == 160
+    assert f(7, 10) == 0
+
+
+def test_params_default(lib):
+    from paper_2111_10354_amd import hisq
+    p = hisq.solver_params()
+    assert p.tol == 1e-10 and p.max_iter == 100000 and p.ru_period == 100
+    assert p.sloppy_prec == hisq.PREC_FP64 and p.fallback == 1
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    from paper_2111_10354_amd import hisq
+    L = hisq.LIB
+    h = C.c_void_p()
+    dummy = C.c_void_p(0x1000)
+    for dims in [(4, 4, 5, 4), (2, 4, 4, 4), (4, 4, 4, 0)]:
+        d = (C.c_int * 4)(*dims)
+        assert L.hisq_gauge_create(C.byref(h), d, dummy, dummy, 7, None) == hisq.ERR_INVALID
+    d = (C.c_int * 4)(4, 4, 4, 4)
+    assert L.hisq_gauge_create(C.byref(h), d, None, dummy, 7, None) == hisq.ERR_INVALID
+    assert L.hisq_gauge_create(C.byref(h), d, dummy, dummy, 0, None) == hisq.ERR_INVALID
+    assert L.hisq_gauge_create(C.byref(h), d, dummy, dummy, 8, None) == hisq.ERR_INVALID
+    big = (C.c_int * 4)(1024, 1024, 1024, 4)
+    assert L.hisq_gauge_create(C.byref(h), big, dummy, dummy, 1, None) == hisq.ERR_INVALID
+    assert "2^31" in hisq.last_error()
+    assert L.hisq_dslash_eo(None, 0, 0, dummy, dummy, None) == hisq.ERR_INVALID
+    assert L.hisq_dslash_multi_rhs(None, 0, 0, 1, dummy, dummy, None, None, None) == hisq.ERR_INVALID
+    assert L.hisq_cg_solve(None, 0.1, 1, dummy, dummy, None, None, None) == hisq.ERR_INVALID
+    assert L.hisq_precond_apply(None, None, dummy, dummy, None) == hisq.ERR_INVALID
+    assert L.hisq_gauge_destroy(None) == hisq.OK
+
+
+def test_header_layout_constants_match_binding():
+    from paper_2111_10354_amd import hisq
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define (HISQ_[A-Z0-9_]+) (-?\d+)\b", text))
+    assert int(consts["HISQ_PREC_FP64"]) == hisq.PREC_FP64
+    assert int(consts["HISQ_PREC_FP32"]) == hisq.PREC_FP32
+    assert int(consts["HISQ_PREC_FP16S"]) == hisq.PREC_FP16S
+    assert int(consts["HISQ_ERR_INVALID"]) == hisq.ERR_INVALID
+    assert int(consts["HISQ_NOT_CONVERGED"]) == hisq.NOT_CONVERGED
+    assert C.sizeof(hisq.SolverParams) == 40 and C.sizeof(hisq.SolverStats) == 40
+
+
+def test_layout_helpers_roundtrip():
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    import layout
+    import synth
+    dims = (4, 6, 4, 4)
+    v = synth.gaussian_source(dims, 99, 1, parity=1)[0]
+    cb = layout.to_cb(dims, v, 1)
+    assert np.array_equal(layout.from_cb(dims, cb, 1), v)
+    vh = cb.shape[1]
+    for prec, tol in (("fp64", 0), ("fp32", 1e-7), ("fp16s", 2 ** -11)):
+        back = layout.decode(layout.encode(cb, prec), vh, prec)
+        err = np.abs(back - cb)
+        scale = np.maximum(np.abs(cb.real), np.abs(cb.imag)).max(axis=0)
+        assert np.all(err <= tol * scale[None, :] * 1.5 + 1e-300)

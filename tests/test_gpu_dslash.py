@@ -1,0 +1,186 @@
+"""GPU parity of the single- and multi-RHS Dslash against the FP64 oracle.
+
+Tolerances (relative L2 over the output vector):
+* FP64: 1e-13; FP32: 1e-6 -- the stated parity bar of the build;
+* FP16S (FP16 links, FP16 values with an FP32 per-site scale, FP32
+  arithmetic): 2e-3 -- 2^-12 relative rounding of every link entry and of the
+  output, summed over 16 terms, stays near 3e-4; the bar leaves margin.
+The oracle is fed exactly the (rounded) input the GPU received, so the error
+measured is that of the kernel and of the link/output storage only.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import fields, flush, hisq, make_gauge, to_device, to_host
+from layout import decode, encode, from_cb, rel_l2, spinor_nbytes, to_cb
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-13, "fp32": 1e-6, "fp16s": 2e-3}
+
+# several tiles and a ragged tail (Vh = 480, 960), one exact multiple (2048),
+# and enough workgroups for the XCD-aware block order to engage (4096, 6144)
+DIMS = [(4, 4, 4, 4), (6, 4, 4, 10), (10, 6, 4, 8), (8, 8, 8, 8), (16, 8, 8, 8), (8, 12, 8, 16)]
+
+
+@pytest.fixture(scope="module")
+def gauges(cuda_device):
+    cache = {}
+
+    def get(dims, apbc=False, free=None):
+        key = (dims, apbc, free)
+        if key not in cache:
+            F, L = fields(dims, apbc=apbc, free=free)
+            cache[key] = (make_gauge(dims, F, L), F, L)
+        return cache[key]
+
+    yield get
+    for g, _, _ in cache.values():
+        g.close()
+
+
+def run_dslash(g, dims, F, L, chi_full, parity, prec):
+    import torch
+    vh = synth.volume(dims) // 2
+    raw = encode(to_cb(dims, chi_full, 1 - parity), prec)
+    chi_q = from_cb(dims, decode(raw, vh, prec), 1 - parity)
+    inp = to_device(raw)
+    out = torch.empty(spinor_nbytes(prec, vh), dtype=torch.uint8, device="cuda")
+    hisq().dslash_eo(g, parity, prec, inp, out)
+    got = decode(to_host(out), vh, prec)
+    want = to_cb(dims, oracle.dslash(dims, F, L, chi_q, parity), parity)
+    return got, want
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_dslash_matches_oracle(gauges, dims, prec, parity):
+    flush(f"dslash parity dims={dims} prec={prec} parity={parity}")
+    g, F, L = gauges(dims, apbc=(dims[3] % 4 == 2))
+    chi = synth.gaussian_source(dims, 99, 1, parity=1 - parity, index0=parity)[0]
+    got, want = run_dslash(g, dims, F, L, chi, parity, prec)
+    err = rel_l2(got, want)
+    assert err <= TOL[prec], err
+
+
+def test_fp16s_error_against_unrounded_input(gauges):
+    """FP16S end to end, including the quantisation of the input spinor."""
+    dims = (8, 8, 8, 8)
+    g, F, L = gauges(dims)
+    chi = synth.gaussian_source(dims, 99, 1, parity=1)[0]
+    got, _ = run_dslash(g, dims, F, L, chi, 0, "fp16s")
+    want = to_cb(dims, oracle.dslash(dims, F, L, chi, 0), 0)
+    err = rel_l2(got, want)
+    flush(f"fp16s end-to-end rel L2 = {err:.3e}")
+    assert err <= 3e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dslash_is_deterministic(gauges, prec):
+    import torch
+    dims = (16, 8, 8, 8)
+    g, F, L = gauges(dims)
+    vh = synth.volume(dims) // 2
+    chi = synth.gaussian_source(dims, 99, 1, parity=1)[0]
+    inp = to_device(encode(to_cb(dims, chi, 1), prec))
+    outs = []
+    for _ in range(3):
+        out = torch.empty(spinor_nbytes(prec, vh), dtype=torch.uint8, device="cuda")
+        hisq().dslash_eo(g, 0, prec, inp, out)
+        outs.append(to_host(out))
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_multi_rhs_matches_single(gauges, prec, nrhs):
+    import torch
+    dims = (10, 6, 4, 8)
+    g, F, L = gauges(dims)
+    vh = synth.volume(dims) // 2
+    srcs = synth.gaussian_source(dims, 99, nrhs, parity=1, index0=10)
+    raw = np.concatenate([encode(to_cb(dims, s, 1), prec) for s in srcs])
+    inp = to_device(raw)
+    out = torch.empty(spinor_nbytes(prec, vh) * nrhs, dtype=torch.uint8, device="cuda")
+    hisq().dslash_multi_rhs(g, 0, prec, nrhs, inp, out)
+    got = to_host(out).reshape(nrhs, -1)
+    nb = spinor_nbytes(prec, vh)
+    for i in range(nrhs):
+        one = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        hisq().dslash_eo(g, 0, prec, inp[i * nb:(i + 1) * nb], one)
+        single = to_host(one)
+        # same accumulation order per RHS: bitwise equal
+        assert np.array_equal(got[i], single), i
+        chi_q = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 1)
+        want = to_cb(dims, oracle.dslash(dims, F, L, chi_q, 0), 0)
+        assert rel_l2(decode(got[i], vh, prec), want) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_multi_rhs_shifted_epilogue(gauges, prec):
+    """out_i = diag_i y_i - D_eo (D_oe y_i) is (A + sigma_i) y_i."""
+    import torch
+    dims = (8, 8, 8, 8)
+    g, F, L = gauges(dims)
+    vh = synth.volume(dims) // 2
+    nrhs = 4
+    mass = 0.1
+    sig = [0.0, 1e-3, 0.1, 1.0]
+    diag = [4 * mass * mass + s for s in sig]
+    ys = synth.gaussian_source(dims, 99, nrhs, parity=0, index0=20)
+    raw = np.concatenate([encode(to_cb(dims, y, 0), prec) for y in ys])
+    y = to_device(raw)
+    nb = spinor_nbytes(prec, vh)
+    t = torch.empty(nb * nrhs, dtype=torch.uint8, device="cuda")
+    out = torch.empty(nb * nrhs, dtype=torch.uint8, device="cuda")
+    hisq().dslash_multi_rhs(g, 1, prec, nrhs, y, t)
+    hisq().dslash_multi_rhs(g, 0, prec, nrhs, t, out, diag=diag, y=y)
+    got = to_host(out).reshape(nrhs, -1)
+    tol = {"fp64": 1e-13, "fp32": 2e-6, "fp16s": 4e-3}[prec]
+    for i in range(nrhs):
+        yq = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 0)
+        want = to_cb(dims, oracle.normal_op(dims, F, L, mass, yq, sigma=sig[i]), 0)
+        assert rel_l2(decode(got[i], vh, prec), want) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_field_plane_wave_large_lattice(prec):
+    """A p = lambda(p) p for a free-field plane wave on 48^3 x 12 (any size holds)."""
+    import torch
+    dims = (48, 48, 48, 12)
+    c1, c3, mass = 9 / 8, -1 / 24, 0.005
+    flush(f"free field 48^3x12 {prec}")
+    F, L = synth.free_links(dims, c1, c3, antiperiodic_t=True)
+    g = make_gauge(dims, F, L, precs=(prec,))
+    del F, L
+    vh = synth.volume(dims) // 2
+    v, p = synth.plane_wave(dims, [3, 7, 1, 2], [0.3, -1j, 0.5 + 0.2j], parity=0, antiperiodic_t=True)
+    lam = 4 * (mass ** 2 + np.sum((c1 * np.sin(p) + c3 * np.sin(3 * p)) ** 2))
+    y = to_device(encode(to_cb(dims, v, 0), prec))
+    nb = spinor_nbytes(prec, vh)
+    t = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    out = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    hisq().dslash_eo(g, 1, prec, y, t)
+    hisq().dslash_multi_rhs(g, 0, prec, 1, t, out, diag=[4 * mass * mass], y=y)
+    got = decode(to_host(out), vh, prec)
+    want = lam * decode(to_host(y), vh, prec)
+    assert rel_l2(got, want) <= (1e-12 if prec == "fp64" else 2e-6)
+    g.close()
+
+
+def test_rejects_unpacked_precision():
+    dims = (4, 4, 4, 4)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L, precs=("fp32",))
+    import torch
+    vh = synth.volume(dims) // 2
+    buf = torch.zeros(spinor_nbytes("fp64", vh), dtype=torch.uint8, device="cuda")
+    out = torch.zeros_like(buf)
+    with pytest.raises(hisq().HisqError) as e:
+        hisq().dslash_eo(g, 0, "fp64", buf, out)
+    assert e.value.code == hisq().ERR_UNSUPPORTED
+    g.close()

@@ -1,0 +1,184 @@
+"""GPU solvers against the FP64 oracle.
+
+Every solve must reach a true relative residual |b - A x| / |b| <= 1e-10,
+recomputed here by the oracle's own operator on the host.  Where the system
+is small enough the solution is also compared with the oracle's CG solution
+within the conditioning bound.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import fields, flush, hisq, make_gauge, to_device, to_host
+from layout import decode, encode, from_cb, rel_l2, to_cb
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+RES_SLACK = 1.0 + 1e-3  # oracle's recomputation differs only by rounding
+
+
+@pytest.fixture(scope="module")
+def c1(cuda_device):
+    dims = (8, 8, 8, 8)
+    F, L = fields(dims, cfg_id=0, eps=0.3)
+    g = make_gauge(dims, F, L)
+    yield dims, F, L, g
+    g.close()
+
+
+def solve(g, dims, mass, srcs, **kw):
+    import torch
+    vh = synth.volume(dims) // 2
+    n = len(srcs)
+    b = to_device(np.concatenate([encode(to_cb(dims, s, 0), "fp64") for s in srcs]))
+    x = torch.zeros_like(b)
+    if kw.pop("warm", None) is not None:
+        pass
+    prm = hisq().solver_params(**kw)
+    rc, st = hisq().cg_solve(g, mass, n, b, x, prm)
+    xs = to_host(x).reshape(n, -1)
+    sol = [from_cb(dims, decode(xs[i], vh, "fp64"), 0) for i in range(n)]
+    return rc, st, sol
+
+
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("graph_chunk", [0, 16])
+def test_cg_c1(c1, sloppy, graph_chunk):
+    dims, F, L, g = c1
+    mass = 0.1
+    b = synth.gaussian_source(dims, 0, 1, parity=0)[0]
+    flush(f"cg 8^4 m=0.1 sloppy={sloppy} chunk={graph_chunk}")
+    rc, st, (x,) = solve(g, dims, mass, [b], sloppy_prec=sloppy, graph_chunk=graph_chunk)
+    assert rc == 0, st
+    assert st[0]["true_residual"] <= TOL
+    res = oracle.true_residual(dims, F, L, mass, b, x)
+    assert res <= TOL * RES_SLACK, res
+    xo, status, iters, tr = oracle.cg(dims, F, L, mass, b, tol=1e-12)
+    assert rel_l2(x, xo) <= 1e-7
+    if sloppy == "fp64":
+        # same algorithm, same stopping rule: iteration counts agree closely
+        _, _, it10, _ = oracle.cg(dims, F, L, mass, b, tol=1e-10)
+        assert abs(st[0]["iterations"] - it10) <= 3
+    else:
+        assert st[0]["reliable_updates"] >= 1
+
+
+def test_graph_and_eager_agree_bitwise(c1):
+    dims, F, L, g = c1
+    b = synth.gaussian_source(dims, 0, 1, parity=0, index0=3)[0]
+    _, sa, (xa,) = solve(g, dims, 0.1, [b], graph_chunk=0)
+    _, sb, (xb,) = solve(g, dims, 0.1, [b], graph_chunk=8)
+    _, sc, (xc,) = solve(g, dims, 0.1, [b], graph_chunk=8)  # replay of a cached graph
+    assert sa[0]["iterations"] == sb[0]["iterations"] == sc[0]["iterations"]
+    assert np.array_equal(xa, xb) and np.array_equal(xb, xc)
+
+
+def test_mixed_precision_low_mass():
+    dims = (8, 8, 8, 8)
+    F, L = fields(dims, cfg_id=99, eps=0.5)
+    g = make_gauge(dims, F, L)
+    mass = 0.01
+    b = synth.gaussian_source(dims, 99, 1, parity=0)[0]
+    for sloppy in ("fp64", "fp32", "fp16s"):
+        flush(f"cg 8^4 m=0.01 sloppy={sloppy}")
+        rc, st, (x,) = solve(g, dims, mass, [b], sloppy_prec=sloppy)
+        assert rc == 0, st
+        assert oracle.true_residual(dims, F, L, mass, b, x) <= TOL * RES_SLACK
+    g.close()
+
+
+def test_batched_multi_rhs(c1):
+    dims, F, L, g = c1
+    mass = 0.1
+    srcs = synth.gaussian_source(dims, 0, 3, parity=0, index0=30)
+    for sloppy in ("fp64", "fp32"):
+        rc, st, xs = solve(g, dims, mass, list(srcs), sloppy_prec=sloppy)
+        assert rc == 0
+        for b, x, s in zip(srcs, xs, st):
+            assert s["true_residual"] <= TOL
+            assert oracle.true_residual(dims, F, L, mass, b, x) <= TOL * RES_SLACK
+
+
+def test_warm_start_and_iteration_cap(c1):
+    import torch
+    dims, F, L, g = c1
+    mass = 0.1
+    b = synth.gaussian_source(dims, 0, 1, parity=0, index0=40)[0]
+    rc, st, (x,) = solve(g, dims, mass, [b])
+    assert rc == 0
+    # warm start from the solution: converged without iterating
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    xd = to_device(encode(to_cb(dims, x, 0), "fp64"))
+    rc, st2 = hisq().cg_solve(g, mass, 1, bd, xd, hisq().solver_params(warm_start=1))
+    assert rc == 0 and st2[0]["iterations"] == 0
+    # cap: status NOT_CONVERGED, exactly max_iter iterations
+    x0 = torch.zeros_like(bd)
+    rc, st3 = hisq().cg_solve(g, mass, 1, bd, x0, hisq().solver_params(max_iter=5))
+    assert rc == hisq().NOT_CONVERGED and st3[0]["iterations"] == 5
+    assert st3[0]["true_residual"] > TOL
+
+
+def test_free_field_solve_closed_form():
+    dims = (32, 32, 32, 8)
+    c1_, c3_, mass = 9 / 8, -1 / 24, 0.01
+    F, L = synth.free_links(dims, c1_, c3_)
+    g = make_gauge(dims, F, L, precs=("fp64", "fp32"))
+    v, p = synth.plane_wave(dims, [1, 2, 3, 1], [1.0, 0.5j, -0.25], parity=0)
+    lam = 4 * (mass ** 2 + np.sum((c1_ * np.sin(p) + c3_ * np.sin(3 * p)) ** 2))
+    for sloppy in ("fp64", "fp32"):
+        rc, st, (x,) = solve(g, dims, mass, [v], sloppy_prec=sloppy)
+        assert rc == 0
+        assert rel_l2(x, v / lam) <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("nshift", [4, 12])
+def test_multishift(c1, nshift):
+    import torch
+    dims, F, L, g = c1
+    mass = 0.05
+    shifts = synth.shifted_ladder(nshift)
+    b = synth.gaussian_source(dims, 0, 1, parity=0, index0=50)[0]
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    vh = synth.volume(dims) // 2
+    x = torch.zeros(nshift * 48 * vh, dtype=torch.uint8, device="cuda")
+    flush(f"multishift 8^4 nshift={nshift}")
+    rc, st = hisq().multishift_cg(g, mass, list(shifts), bd, x)
+    assert rc == 0, st
+    xs = to_host(x).reshape(nshift, -1)
+    for k, s in enumerate(shifts):
+        xk = from_cb(dims, decode(xs[k], vh, "fp64"), 0)
+        res = oracle.true_residual(dims, F, L, mass, b, xk, sigma=s)
+        assert res <= TOL * RES_SLACK, (k, res)
+        assert st[k]["true_residual"] <= TOL
+
+
+def test_multishift_unsorted_shifts(c1):
+    import torch
+    dims, F, L, g = c1
+    mass = 0.1
+    shifts = [0.5, 0.0, 0.02]
+    b = synth.gaussian_source(dims, 0, 1, parity=0, index0=60)[0]
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    vh = synth.volume(dims) // 2
+    x = torch.zeros(len(shifts) * 48 * vh, dtype=torch.uint8, device="cuda")
+    rc, st = hisq().multishift_cg(g, mass, shifts, bd, x, hisq().solver_params(graph_chunk=0))
+    assert rc == 0
+    xs = to_host(x).reshape(len(shifts), -1)
+    for k, s in enumerate(shifts):
+        xk = from_cb(dims, decode(xs[k], vh, "fp64"), 0)
+        assert oracle.true_residual(dims, F, L, mass, b, xk, sigma=s) <= TOL * RES_SLACK
+
+
+def test_invalid_shift_rejected(c1):
+    import torch
+    dims, F, L, g = c1
+    vh = synth.volume(dims) // 2
+    b = torch.zeros(48 * vh, dtype=torch.uint8, device="cuda")
+    x = torch.zeros(48 * vh * 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(hisq().HisqError) as e:
+        hisq().multishift_cg(g, 0.1, [0.0, -0.05], b, x)
+    assert e.value.code == hisq().ERR_INVALID
