@@ -1,0 +1,291 @@
+"""Benchmark: HISQ even/odd Dslash GB/s against the HBM roofline, and CG time
+to |r|/|b| < 1e-10, plain FP64 CG vs the mixed-precision form.
+
+One timed step = one FP32 single-parity Dslash over the whole 96^3 x 24
+lattice (one GPU's share of a large-volume HISQ lattice), 1 RHS, inputs
+resident in HBM.  Around it the run also measures the FP64 / FP16S /
+multi-RHS Dslash variants, CG solves at 32^3 x 8 (plain FP64 vs mixed
+FP32 and FP16S with reliable updates), a sampled parity check of the timed
+launch against the FP64 oracle, and the oracle's own Dslash on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FLOP_PER_SITE = 1146
+METRIC = "Dslash GB/s (% HBM peak); CG time to |r|/|b|<1e-10, plain vs chosen form"
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def cb_gather(dims, vec_full, parity):
+    """[V,3] full-lattice vector -> [3, Vh] planes of one parity (checkerboard order)."""
+    import synth
+    s = np.nonzero(synth.site_parity(dims) == parity)[0]
+    return np.ascontiguousarray(vec_full[s].T), s
+
+
+def encode(cb, prec):
+    if prec == "fp64":
+        return np.ascontiguousarray(cb.astype(np.complex128)).view(np.uint8).ravel()
+    if prec == "fp32":
+        return np.ascontiguousarray(cb.astype(np.complex64)).view(np.uint8).ravel()
+    re = np.stack([cb.real, cb.imag], axis=-1)
+    scale = np.abs(re).max(axis=(0, 2)).astype(np.float32)
+    inv = np.where(scale > 0, 1.0 / scale.astype(np.float64), 0.0)
+    halves = (re * inv[None, :, None]).astype(np.float16)
+    return np.concatenate([halves.view(np.uint8).ravel(), scale.view(np.uint8).ravel()])
+
+
+def counter_traffic(dims):
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+    counter summary, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"dslash_fp32_{'x'.join(map(str, dims))}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2111_10354_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, n), "rb").read() for n in ("dslash.hip", "hisq_internal.h", "pack.hip"))
+    if hashlib.sha256(src).hexdigest() != rec.get("kernel_sources_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"] / 1e9  # GB, like `achieved`
+
+
+def time_launches(fn, steps, warmup):
+    """Average time of fn() (launches on the current stream) from HIP events."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dims", type=str, default="96,96,96,24")
+    ap.add_argument("--quick", action="store_true", help="skip CG and the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--only-fp32", action="store_true", help="time only the headline kernel")
+    ap.add_argument("--fields-cache", type=str, default=None,
+                    help="directory to save / reuse the generated link fields (profiling re-runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 4 GiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 4 << 30
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        ms = time_launches(lambda: dst.copy_(src), 5, 1)
+        log(f"copy of {n >> 20} MiB: {ms:.3f} ms, {2 * n / (ms * 1e-3) / 1e9:.0f} GB/s (read+write)")
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms": ms,
+                          "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the lattice would be split by domain decomposition with halo exchange; not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import synth  # input generator only
+    dims = tuple(int(v) for v in args.dims.split(","))
+    V = synth.volume(dims)
+    vh = V // 2
+    cfg = synth.CONFIGS["c5"]
+    t0 = time.time()
+    cache = None
+    if args.fields_cache:
+        tag = f"hisq_{'x'.join(map(str, dims))}_c5_eps{cfg['eps']}"
+        cache = (os.path.join(args.fields_cache, tag + "_fat.npy"), os.path.join(args.fields_cache, tag + "_long.npy"))
+    if cache and all(os.path.exists(p) for p in cache):
+        log(f"loading cached fields {cache[0]}")
+        F, L = np.load(cache[0]), np.load(cache[1])
+    else:
+        log(f"generating fields {dims} (eps={cfg['eps']}) on {min(16, os.cpu_count() or 1)} workers")
+        F, L = synth.hisq_links(dims, synth.CFG_IDS["c5"], cfg["eps"])
+        if cache:
+            os.makedirs(args.fields_cache, exist_ok=True)
+            np.save(cache[0], F)
+            np.save(cache[1], L)
+    log(f"fields ready in {time.time() - t0:.1f}s")
+    chi = synth.gaussian_source(dims, synth.CFG_IDS["c5"], 1, parity=1)[0]
+
+    import torch
+    from paper_2111_10354_amd import hisq
+
+    precs = ("fp32",) if args.only_fp32 else ("fp64", "fp32", "fp16s")
+    fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
+    g = hisq.Gauge(dims, fd, ld, precs)
+    torch.cuda.synchronize()
+    del fd, ld
+    torch.cuda.empty_cache()
+    log(f"gauge packed: {g.device_bytes() / 2**30:.1f} GiB of link copies")
+
+    cb, odd_sites = cb_gather(dims, chi, 1)
+    even_sites = np.nonzero(synth.site_parity(dims) == 0)[0]
+    bufs = {}
+    for p in precs:
+        inp = torch.from_numpy(encode(cb, p)).cuda()
+        out = torch.empty(hisq.spinor_bytes(p, vh), dtype=torch.uint8, device="cuda")
+        bufs[p] = (inp, out)
+
+    def algo_bytes(p, nrhs=1):
+        link = {"fp64": 8, "fp32": 4, "fp16s": 2}[p] * 16 * 18
+        spin = {"fp64": 48, "fp32": 24, "fp16s": 16}[p]
+        return vh * (link + nrhs * 2 * spin)
+
+    # ---- headline: FP32 single-RHS single-parity Dslash
+    inp, out = bufs["fp32"]
+    ms = time_launches(lambda: hisq.dslash_eo(g, 0, "fp32", inp, out), args.steps, args.warmup)
+    gbs = algo_bytes("fp32") / (ms * 1e-3) / 1e9
+    log(f"FP32 Dslash: {ms:.3f} ms/launch, {gbs:.0f} GB/s algorithmic ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+
+    # sampled parity of the timed launch against the oracle
+    import oracle  # test infrastructure: used here only for the parity sample and cpu_baseline
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.complex64).reshape(3, vh)
+    rng = np.random.default_rng(7)
+    hs = np.sort(rng.choice(vh, size=256, replace=False))
+    chi_q = np.zeros_like(chi)
+    chi_q[odd_sites] = cb.astype(np.complex64).astype(np.complex128).T
+    want = oracle.dslash_sites(dims, F, L, chi_q, even_sites[hs])
+    perr = float(np.linalg.norm(got[:, hs].T - want) / np.linalg.norm(want))
+    log(f"sampled parity (256 sites) FP32 vs oracle: rel L2 {perr:.2e}")
+
+    variants = {"fp32": {"ms": ms, "gbs": gbs}}
+    if not args.only_fp32:
+        for p in ("fp64", "fp16s"):
+            i2, o2 = bufs[p]
+            m2 = time_launches(lambda: hisq.dslash_eo(g, 0, p, i2, o2), max(10, args.steps // 2), 3)
+            variants[p] = {"ms": m2, "gbs": algo_bytes(p) / (m2 * 1e-3) / 1e9}
+            log(f"{p} Dslash: {m2:.3f} ms, {variants[p]['gbs']:.0f} GB/s")
+        # 4 RHS (the workload's batch) through the multi-RHS kernel
+        n = cfg["nrhs"]
+        srcs = synth.gaussian_source(dims, synth.CFG_IDS["c5"], n, parity=1, index0=1)
+        for p in ("fp32", "fp16s"):
+            raw = np.concatenate([encode(cb_gather(dims, s, 1)[0], p) for s in srcs])
+            i4 = torch.from_numpy(raw).cuda()
+            o4 = torch.empty(hisq.spinor_bytes(p, vh) * n, dtype=torch.uint8, device="cuda")
+            m4 = time_launches(lambda: hisq.dslash_multi_rhs(g, 0, p, n, i4, o4), max(10, args.steps // 2), 3)
+            variants[f"{p}_x{n}rhs"] = {"ms": m4, "gbs": algo_bytes(p, n) / (m4 * 1e-3) / 1e9,
+                                        "ms_per_rhs": m4 / n}
+            log(f"{p} x{n} RHS Dslash: {m4:.3f} ms ({m4 / n:.3f} ms/RHS), {variants[f'{p}_x{n}rhs']['gbs']:.0f} GB/s")
+            del i4, o4
+        for k, v in variants.items():
+            v["gflops"] = FLOP_PER_SITE * vh * (4 if "x4" in k else 1) / (v["ms"] * 1e-3) / 1e9
+            v["frac_hbm_peak"] = v["gbs"] / HBM_PEAK_GBS
+
+    # ---- CPU baseline: the FP64 oracle's Dslash on this lattice, host cores
+    cpu = None
+    if not (args.quick or args.no_cpu):
+        nthr = oracle.num_threads()
+        log(f"oracle Dslash on the host ({nthr} threads)")
+        reps, t_tot = 0, 0.0
+        while t_tot < 10.0 and reps < 20:
+            t1 = time.time()
+            oracle.dslash(dims, F, L, chi, 0)
+            t_tot += time.time() - t1
+            reps += 1
+        t_one = t_tot / reps
+        cpu = {"value": algo_bytes("fp64") / t_one / 1e9, "unit": "GB/s", "cores": nthr, "kind": "oracle",
+               "sample": f"{reps} full single-parity FP64 Dslash applications on the same {dims} lattice "
+                         f"({t_one:.2f} s each); GB/s counts the FP64 algorithmic bytes (2400 B/site)"}
+        log(f"oracle: {t_one:.2f} s per Dslash = {cpu['value']:.2f} GB/s")
+    del F, L
+
+    # ---- CG time to solution on the 32^3 x 8 workload
+    cg = None
+    if not (args.quick or args.no_cg):
+        cg = run_cg(hisq, torch)
+
+    result = {
+        "metric": METRIC,
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"HISQ single-parity Dslash, {'x'.join(map(str, dims))} lattice, FP32 links "
+                               f"and spinors, 1 RHS, seeded links (eps={cfg['eps']})",
+                   "dims": list(dims), "sites_per_parity": vh, "bytes_per_step": algo_bytes("fp32"),
+                   "flop_per_site": FLOP_PER_SITE},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dims),
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
+        "cpu_baseline": cpu,
+        "parity_sample_rel_l2": perr,
+        "variants": variants,
+        "cg": cg,
+    }
+    g.close()
+    print(json.dumps(result), flush=True)
+
+
+def run_cg(hisq, torch):
+    import synth
+    c = synth.CONFIGS["c2"]
+    dims, mass = c["dims"], c["mass"]
+    vh = synth.volume(dims) // 2
+    log(f"CG workload {dims} m={mass}: generating fields")
+    F, L = synth.hisq_links(dims, synth.CFG_IDS["c2"], c["eps"])
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32", "fp16s"))
+    b = synth.gaussian_source(dims, synth.CFG_IDS["c2"], 1, parity=0)[0]
+    bcb, _ = cb_gather(dims, b, 0)
+    bd = torch.from_numpy(encode(bcb, "fp64")).cuda()
+    out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, 1 Gaussian RHS, tol 1e-10 (true residual)"}
+    for name, sloppy in (("plain_fp64", "fp64"), ("mixed_fp32", "fp32"), ("mixed_fp16s", "fp16s")):
+        prm = hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25)
+        x = torch.zeros_like(bd)
+        hisq.cg_solve(g, mass, 1, bd, x, hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25, max_iter=50))
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.time()
+        rc, st = hisq.cg_solve(g, mass, 1, bd, x, prm)
+        wall = time.time() - t1
+        out[name] = {"status": rc, "seconds": round(wall, 4), "iterations": st[0]["iterations"],
+                     "reliable_updates": st[0]["reliable_updates"],
+                     "true_residual": st[0]["true_residual"]}
+        log(f"CG {name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
+    best = min(("mixed_fp32", "mixed_fp16s"), key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
+    out["chosen"] = best
+    out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
+    g.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()
