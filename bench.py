@@ -35,22 +35,15 @@ def log(msg):
 
 
 def cb_gather(dims, vec_full, parity):
-    """[V,3] full-lattice vector -> [3, Vh] planes of one parity (checkerboard order)."""
-    import synth
-    s = np.nonzero(synth.site_parity(dims) == parity)[0]
-    return np.ascontiguousarray(vec_full[s].T), s
+    """[V,3] full-lattice vector -> [3, Vh] values of one parity (checkerboard order)."""
+    from paper_2111_10354_amd import layout
+    s = layout.parity_sites(dims, parity)
+    return layout.to_planes(vec_full, s), s
 
 
 def encode(cb, prec):
-    if prec == "fp64":
-        return np.ascontiguousarray(cb.astype(np.complex128)).view(np.uint8).ravel()
-    if prec == "fp32":
-        return np.ascontiguousarray(cb.astype(np.complex64)).view(np.uint8).ravel()
-    re = np.stack([cb.real, cb.imag], axis=-1)
-    scale = np.abs(re).max(axis=(0, 2)).astype(np.float32)
-    inv = np.where(scale > 0, 1.0 / scale.astype(np.float64), 0.0)
-    halves = (re * inv[None, :, None]).astype(np.float16)
-    return np.concatenate([halves.view(np.uint8).ravel(), scale.view(np.uint8).ravel()])
+    from paper_2111_10354_amd import layout
+    return layout.encode(cb, prec)
 
 
 def counter_traffic(dims):
@@ -150,7 +143,7 @@ def main():
     log(f"gauge packed: {g.device_bytes() / 2**30:.1f} GiB of link copies")
 
     cb, odd_sites = cb_gather(dims, chi, 1)
-    even_sites = np.nonzero(synth.site_parity(dims) == 0)[0]
+    even_sites = cb_gather(dims, chi, 0)[1]
     bufs = {}
     for p in precs:
         inp = torch.from_numpy(encode(cb, p)).cuda()
@@ -171,11 +164,12 @@ def main():
     # sampled parity of the timed launch against the oracle
     import oracle  # test infrastructure: used here only for the parity sample and cpu_baseline
     torch.cuda.synchronize()
-    got = out.cpu().numpy().view(np.complex64).reshape(3, vh)
+    from paper_2111_10354_amd import layout
+    got = layout.decode(out.cpu().numpy(), vh, "fp32")
     rng = np.random.default_rng(7)
     hs = np.sort(rng.choice(vh, size=256, replace=False))
     chi_q = np.zeros_like(chi)
-    chi_q[odd_sites] = cb.astype(np.complex64).astype(np.complex128).T
+    chi_q[odd_sites] = layout.decode(encode(cb, "fp32"), vh, "fp32").T
     want = oracle.dslash_sites(dims, F, L, chi_q, even_sites[hs])
     perr = float(np.linalg.norm(got[:, hs].T - want) / np.linalg.norm(want))
     log(f"sampled parity (256 sites) FP32 vs oracle: rel L2 {perr:.2e}")

@@ -21,14 +21,18 @@
  *   D maps one parity to the other.  Normal operator on even sites:
  *   A = 4 m^2 - D_eo D_oe  ( = (D^+ D + 4 m^2) restricted to even sites, HPD).
  *
- * Spinor (colour-vector) buffers, one parity, "[3][Vh]" = colour-major planes:
- *   HISQ_PREC_FP64  : complex double (re,im interleaved) [3][Vh]     48*Vh bytes
- *   HISQ_PREC_FP32  : complex float                      [3][Vh]     24*Vh bytes
- *   HISQ_PREC_FP16S : complex half [3][Vh] (12*Vh bytes) followed by
- *                     float scale[Vh]; value = scale[h] * half      16*Vh bytes
- *                     (scale = max |re|,|im| over the site's 6 reals).
- *   nrhs buffers are stacked back to back: [nrhs][3][Vh].
- *   hisq_spinor_bytes() returns the size of one such buffer.
+ * Spinor (colour-vector) buffers, one parity, sites in checkerboard order h:
+ *   HISQ_PREC_FP64  : complex double [3][Vh], colour-major planes   48*Vh bytes
+ *                     (colour c of site h at complex index c*Vh + h)
+ *   HISQ_PREC_FP32  : plane A float[Vh][4] = (re0, im0, re1, im1), then
+ *                     plane B float[Vh][2] = (re2, im2)            24*Vh bytes
+ *   HISQ_PREC_FP16S : one 16-byte record per site: half[6] = (re0, im0, re1,
+ *                     im1, re2, im2) then float scale; value = scale * half,
+ *                     scale = max |re|,|im| over the site's 6 reals,
+ *                     halves rounded to nearest even               16*Vh bytes
+ *   nrhs buffers are stacked back to back: [nrhs][one buffer].
+ *   hisq_spinor_bytes() returns the size of one buffer.  Every spinor pointer
+ *   must be 16-byte aligned.
  *
  * Memory and streams: every data pointer is a DEVICE pointer on the current
  * HIP device unless stated otherwise.  The caller owns its buffers; the library

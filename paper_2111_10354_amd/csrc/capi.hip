@@ -34,6 +34,14 @@ static int check_dims(const int *dims) {
     return HISQ_OK;
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+static int check_spinors(const void *a, const void *b, const void *c = nullptr) {
+    if (!aligned16(a) || !aligned16(b) || (c && !aligned16(c)))
+        return fail(HISQ_ERR_INVALID, "spinor buffers must be 16-byte aligned");
+    return HISQ_OK;
+}
+
 static int check_handle(hisq_gauge_t g) {
     if (!g) return fail(HISQ_ERR_INVALID, "gauge handle is NULL");
     return HISQ_OK;
@@ -172,6 +180,7 @@ int hisq_dslash_eo(hisq_gauge_t g, int out_parity, int prec, const void *in, voi
     if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
     if (!in || !out) return fail(HISQ_ERR_INVALID, "in and out are required");
     if (in == out) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
+    if ((rc = check_spinors(in, out))) return rc;
     return gauge_dslash(g, out_parity, prec, prec, prec, 1, in, out, nullptr, nullptr, nullptr, nullptr,
                         (hipStream_t)stream);
 }
@@ -186,6 +195,7 @@ int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, co
     if (!in || !out) return fail(HISQ_ERR_INVALID, "in and out are required");
     if (in == out) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
     if ((diag == nullptr) != (y == nullptr)) return fail(HISQ_ERR_INVALID, "diag and y go together");
+    if ((rc = check_spinors(in, out, y))) return rc;
     hipStream_t s = (hipStream_t)stream;
     const double *ddev = nullptr;
     double *part = nullptr;
@@ -214,6 +224,7 @@ int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double
     if (nrhs < 1) return fail(HISQ_ERR_INVALID, "nrhs must be >= 1");
     if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
     if (b == x) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
+    if ((rc = check_spinors(b, x))) return rc;
     std::lock_guard<std::mutex> lk(g->mu);
     return cg_solve(g, mass, nrhs, b, x, nullptr, prm, st, (hipStream_t)stream);
 }
@@ -233,6 +244,7 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
         if (!std::isfinite(shifts[k]) || !(shifts[k] + 4.0 * mass * mass > 0.0))
             return fail(HISQ_ERR_INVALID, "every shift must be finite with sigma + 4 m^2 > 0");
     if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
+    if ((rc = check_spinors(b, x))) return rc;
     std::lock_guard<std::mutex> lk(g->mu);
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }

@@ -33,14 +33,6 @@ Geom make_geom(const int dims[4]) {
 
 int dslash_grid_blocks(const Geom &g, int block) { return (g.vh + block - 1) / block; }
 
-template <int F>
-struct LinkView;
-template <> struct LinkView<F64> { static Links<F64> make(const void *p, int vh) { return {(const d2v *)p, vh}; } };
-template <> struct LinkView<F32> { static Links<F32> make(const void *p, int vh) { return {(const float *)p, vh}; } };
-template <> struct LinkView<H16> {
-    static Links<H16> make(const void *p, int vh) { return {(const unsigned int *)p, vh}; }
-};
-
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -56,8 +48,9 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Sp
                                                      const CgState *__restrict__ skip, int parity,
                                                      int nrhs) {
     typedef typename RealOf<LF>::T R;
+    constexpr int G = LinkGroup<LF>::G;
     const int nb = gridDim.x;
-    const int blk = xcd_block(blockIdx.x, nb);
+    const int blk = blockIdx.x;
     const int h = blk * blockDim.x + threadIdx.x;
     const int r0 = blockIdx.y * TILE;
     if (skip) {
@@ -81,12 +74,13 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Sp
             for (int c = 0; c < 3; ++c) acc[r][c] = {R(0), R(0)};
 
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
+        for (int gi = 0; gi < 16 / G; ++gi) {
+            cx<R> w[9 * G];
+            links.load_group(gi, h, w);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int nbh = hop_index(g, sc, h, mu, slot_dist(j));
-                cx<R> w[9];
-                links.load(4 * mu + j, h, w);
+            for (int sl = 0; sl < G; ++sl) {
+                const int k = gi * G + sl;
+                const int nbh = hop_index(g, sc, h, k >> 2, slot_dist(k & 3));
 #pragma unroll
                 for (int r = 0; r < TILE; ++r) {
                     if (TILE > 1 && r0 + r >= nrhs) break;
@@ -96,7 +90,7 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Sp
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) cmac(acc[r][a], w[3 * a + b], v[b]);
+                        for (int b = 0; b < 3; ++b) cmac(acc[r][a], w[9 * sl + 3 * a + b], v[b]);
                 }
             }
         }
@@ -126,7 +120,9 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Sp
             cx<RO> oo[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) oo[c] = {(RO)o[c].re, (RO)o[c].im};
-            dst.store(h, oo);
+            // streaming store: interleaving ordinary write-backs with the link
+            // stream costs far more HBM time than the 2% of bytes they carry
+            dst.store_nt(h, oo);
         }
     }
 
@@ -153,7 +149,7 @@ template <int LF, int SI, int SO, int TILE, bool EPI>
 static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     dim3 block(a.block);
     dim3 grid(dslash_grid_blocks(g, a.block), (a.nrhs + TILE - 1) / TILE);
-    Links<LF> L = LinkView<LF>::make(a.links, g.vh);
+    Links<LF> L{a.links};
     Spinor<SI> in = spinor_view<SI>(const_cast<void *>(a.in), g.vh);
     Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
     Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);

@@ -17,6 +17,7 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 template <class T>
@@ -84,21 +85,13 @@ __device__ __forceinline__ int hop_index(const Geom &g, const SiteCoord &s, int 
 // Hop of link slot k = 4*mu + j: j = 0 -> +1, 1 -> -1, 2 -> +3, 3 -> -3.
 __device__ __forceinline__ constexpr int slot_dist(int j) { return j == 0 ? 1 : j == 1 ? -1 : j == 2 ? 3 : -3; }
 
-// Workgroups are dealt round-robin to the 8 XCDs; remap so each XCD walks a
-// contiguous range of sites and its L2 sees the x/y/z neighbours it reuses.
-__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
-    const int per = nblocks >> 3;
-    if (per == 0 || (nblocks & 7)) return bid;
-    return (bid & 7) * per + (bid >> 3);
-}
-
 // ------------------------------------------------------------------ formats
 enum Fmt { F64 = HISQ_PREC_FP64, F32 = HISQ_PREC_FP32, H16 = HISQ_PREC_FP16S };
 
 template <int F> struct RealOf { typedef float T; };
 template <> struct RealOf<F64> { typedef double T; };
 
-// Spinor field of one parity in colour-major planes (public layout).
+// Spinor field of one parity in the public layouts (include/hisq.h).
 template <int F> struct Spinor;
 
 template <> struct Spinor<F64> {
@@ -117,51 +110,65 @@ template <> struct Spinor<F64> {
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[(size_t)c * vh + h] = d2v{v[c].re, v[c].im};
     }
+    // streaming store: the written field is not re-read by this kernel
+    __device__ __forceinline__ void store_nt(int h, const cx<double> v[3]) const {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(d2v{v[c].re, v[c].im}, p + (size_t)c * vh + h);
+    }
 };
 
+// FP32: plane A = colours 0,1 as float4 [vh], plane B = colour 2 as float2 [vh]
+// (two loads per site instead of three).
 template <> struct Spinor<F32> {
-    f2v *p;
+    float *p;
     int vh;
-    __device__ __forceinline__ Spinor rhs(int i) const { return {p + (size_t)i * 3 * vh, vh}; }
+    __device__ __forceinline__ Spinor rhs(int i) const { return {p + (size_t)i * 6 * vh, vh}; }
     __device__ __forceinline__ void load(int h, cx<float> v[3]) const {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            f2v a = p[(size_t)c * vh + h];
-            v[c] = {a.x, a.y};
-        }
+        const f4v a = ((const f4v *)p)[h];
+        const f2v b = ((const f2v *)(p + (size_t)4 * vh))[h];
+        v[0] = {a.x, a.y};
+        v[1] = {a.z, a.w};
+        v[2] = {b.x, b.y};
     }
     __device__ __forceinline__ void store(int h, const cx<float> v[3]) const {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) p[(size_t)c * vh + h] = f2v{v[c].re, v[c].im};
+        ((f4v *)p)[h] = f4v{v[0].re, v[0].im, v[1].re, v[1].im};
+        ((f2v *)(p + (size_t)4 * vh))[h] = f2v{v[2].re, v[2].im};
+    }
+    __device__ __forceinline__ void store_nt(int h, const cx<float> v[3]) const {
+        __builtin_nontemporal_store(f4v{v[0].re, v[0].im, v[1].re, v[1].im}, (f4v *)p + h);
+        __builtin_nontemporal_store(f2v{v[2].re, v[2].im}, (f2v *)(p + (size_t)4 * vh) + h);
     }
 };
 
-// FP16 values with one FP32 scale per site: value = scale * half.
+// FP16S: one 16-byte record per site, {c0, c1, c2 as half2, scale as float};
+// value = scale * half, scale = max |re|,|im| over the site (one load per site).
 template <> struct Spinor<H16> {
-    h2v *p;      // [3][vh]
-    float *s;    // [vh], right after the planes
+    u4v *p;
     int vh;
-    // one buffer = 16*vh bytes = 4*vh words, planes and scales move together
-    __device__ __forceinline__ Spinor rhs(int i) const {
-        return {p + (size_t)i * 4 * vh, s + (size_t)i * 4 * vh, vh};
-    }
+    __device__ __forceinline__ Spinor rhs(int i) const { return {p + (size_t)i * vh, vh}; }
     __device__ __forceinline__ void load(int h, cx<float> v[3]) const {
-        const float sc = s[h];
+        const u4v rec = p[h];
+        const h8v a = __builtin_bit_cast(h8v, rec);
+        // element to a scalar first: bit-casting rec.w directly reads element 0
+        const unsigned int sw = rec.w;
+        const float sc = __builtin_bit_cast(float, sw);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            f2v a = __builtin_convertvector(p[(size_t)c * vh + h], f2v);
-            v[c] = {a.x * sc, a.y * sc};
-        }
+        for (int c = 0; c < 3; ++c) v[c] = {(float)a[2 * c] * sc, (float)a[2 * c + 1] * sc};
     }
-    __device__ __forceinline__ void store(int h, const cx<float> v[3]) const {
+    static __device__ __forceinline__ u4v encode(const cx<float> v[3]) {
         float m = 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
+        unsigned int wd[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            p[(size_t)c * vh + h] = __builtin_convertvector((f2v{v[c].re * inv, v[c].im * inv}), h2v);
-        s[h] = m;
+            wd[c] = __builtin_bit_cast(unsigned int, __builtin_convertvector((f2v{v[c].re * inv, v[c].im * inv}), h2v));
+        return u4v{wd[0], wd[1], wd[2], __builtin_bit_cast(unsigned int, m)};
+    }
+    __device__ __forceinline__ void store(int h, const cx<float> v[3]) const { p[h] = encode(v); }
+    __device__ __forceinline__ void store_nt(int h, const cx<float> v[3]) const {
+        __builtin_nontemporal_store(encode(v), p + h);
     }
 };
 
@@ -170,11 +177,9 @@ inline Spinor<F> spinor_view(void *ptr, int vh);
 template <>
 inline Spinor<F64> spinor_view<F64>(void *ptr, int vh) { return {(d2v *)ptr, vh}; }
 template <>
-inline Spinor<F32> spinor_view<F32>(void *ptr, int vh) { return {(f2v *)ptr, vh}; }
+inline Spinor<F32> spinor_view<F32>(void *ptr, int vh) { return {(float *)ptr, vh}; }
 template <>
-inline Spinor<H16> spinor_view<H16>(void *ptr, int vh) {
-    return {(h2v *)ptr, (float *)((char *)ptr + (size_t)12 * vh), vh};
-}
+inline Spinor<H16> spinor_view<H16>(void *ptr, int vh) { return {(u4v *)ptr, vh}; }
 
 inline size_t spinor_bytes(int f, int64_t vh) {
     switch (f) {
@@ -185,73 +190,76 @@ inline size_t spinor_bytes(int f, int64_t vh) {
     }
 }
 
-// Packed links for one output parity: 16 slots (k = 4 mu + j), each slot a
-// block of 9 complex entries per output site, stored so that one wavefront
-// reads whole contiguous planes:
-//   F64: [16][9][vh] double2
-//   F32: [16] { float4 [4][vh] (entries 0..7), float2 [vh] (entry 8) }
-//   H16: [16] { 8-half [2][vh] (entries 0..7), half2  [vh] (entry 8) }
-// Slot k of output site x already holds the factor that multiplies the
-// neighbour spinor: F_mu(x), -F_mu(x-mu)^+, L_mu(x), -L_mu(x-3mu)^+.
-inline size_t link_slot_bytes(int f, int64_t vh) {
-    switch (f) {
-        case F64: return (size_t)144 * vh;
-        case F32: return (size_t)72 * vh;
-        case H16: return (size_t)36 * vh;
-        default: return 0;
-    }
+// Packed links for one output parity.  Slot k = 4 mu + j of output site x
+// holds the matrix that multiplies the neighbour colour vector:
+//   j = 0: F_mu(x), 1: -F_mu(x-mu)^+, 2: L_mu(x), 3: -L_mu(x-3mu)^+.
+// Consecutive slots are grouped so that one group is 144 bytes = nine 16-byte
+// units per site: a group is 1 link in FP64, 2 links in FP32, 4 links in FP16
+// (the group's links' complex entries concatenated, row-major).  Sites are
+// tiled by 64 (one wavefront), and a tile stores, group by group and unit by
+// unit, the 64 sites' 16-byte units back to back:
+//   byte offset of (site h, group gi, unit e) =
+//       (((h / 64) * NG + gi) * 9 + e) * 1024 + (h % 64) * 16,   NG = 16 / G.
+// One load instruction of a wavefront reads 1 KiB contiguously and the whole
+// wavefront's 16 links are one contiguous stream: every link byte is read
+// exactly once per Dslash, at the pattern a plain streaming read uses.
+constexpr int LINK_TILE = 64;
+template <int F> struct LinkGroup { static constexpr int G = 1; };
+template <> struct LinkGroup<F32> { static constexpr int G = 2; };
+template <> struct LinkGroup<H16> { static constexpr int G = 4; };
+
+inline int link_group_size(int f) { return f == F64 ? 1 : f == F32 ? 2 : 4; }
+inline size_t link_parity_bytes(int f, int64_t vh) {
+    const int64_t tiles = (vh + LINK_TILE - 1) / LINK_TILE;
+    return (size_t)tiles * (16 / link_group_size(f)) * 9 * 1024;
 }
-inline size_t link_parity_bytes(int f, int64_t vh) { return 16 * link_slot_bytes(f, vh); }
+
+__device__ __forceinline__ const u4v *link_unit_ptr(const void *base, int ng, int gi, int h) {
+    return (const u4v *)base + ((size_t)((h >> 6) * ng + gi) * 9) * 64 + (h & 63);
+}
 
 template <int F> struct Links;
 
 template <> struct Links<F64> {
-    const d2v *p;  // parity block
-    int vh;
-    __device__ __forceinline__ void load(int k, int h, cx<double> w[9]) const {
-        const d2v *b = p + (size_t)k * 9 * vh + h;
+    const void *p;
+    // the G*9 = 9 complex entries of group gi (= slot gi)
+    __device__ __forceinline__ void load_group(int gi, int h, cx<double> w[9]) const {
+        const u4v *b = link_unit_ptr(p, 16, gi, h);
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            d2v a = __builtin_nontemporal_load(b + (size_t)e * vh);
+            d2v a = __builtin_bit_cast(d2v, __builtin_nontemporal_load(b + e * 64));
             w[e] = {a.x, a.y};
         }
     }
 };
 
 template <> struct Links<F32> {
-    const float *p;
-    int vh;
-    __device__ __forceinline__ void load(int k, int h, cx<float> w[9]) const {
-        const float *b = p + (size_t)k * 18 * vh;
+    const void *p;
+    // 18 complex entries: slots 2 gi and 2 gi + 1
+    __device__ __forceinline__ void load_group(int gi, int h, cx<float> w[18]) const {
+        const u4v *b = link_unit_ptr(p, 8, gi, h);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            f4v a = __builtin_nontemporal_load((const f4v *)(b + (size_t)q * 4 * vh) + h);
-            w[2 * q] = {a.x, a.y};
-            w[2 * q + 1] = {a.z, a.w};
+        for (int e = 0; e < 9; ++e) {
+            f4v a = __builtin_bit_cast(f4v, __builtin_nontemporal_load(b + e * 64));
+            w[2 * e] = {a.x, a.y};
+            w[2 * e + 1] = {a.z, a.w};
         }
-        f2v a = __builtin_nontemporal_load((const f2v *)(b + (size_t)16 * vh) + h);
-        w[8] = {a.x, a.y};
     }
 };
 
 template <> struct Links<H16> {
-    const unsigned int *p;  // in 32-bit words; one word = one complex half
-    int vh;
-    __device__ __forceinline__ void load(int k, int h, cx<float> w[9]) const {
-        const unsigned int *b = p + (size_t)k * 9 * vh;
+    const void *p;
+    // 36 complex entries: slots 4 gi .. 4 gi + 3
+    __device__ __forceinline__ void load_group(int gi, int h, cx<float> w[36]) const {
+        const u4v *b = link_unit_ptr(p, 4, gi, h);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            u4v a = __builtin_nontemporal_load((const u4v *)(b + (size_t)q * 4 * vh) + h);
+        for (int e = 0; e < 9; ++e) {
+            // reinterpret all 16 bytes at once: bit-casting a single element
+            // of the loaded vector (a[q]) was compiled as if q were 0
+            const h8v a = __builtin_bit_cast(h8v, __builtin_nontemporal_load(b + e * 64));
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                unsigned int wd = a[e];
-                f2v f = __builtin_convertvector(__builtin_bit_cast(h2v, wd), f2v);
-                w[4 * q + e] = {f.x, f.y};
-            }
+            for (int q = 0; q < 4; ++q) w[4 * e + q] = {(float)a[2 * q], (float)a[2 * q + 1]};
         }
-        unsigned int wd = __builtin_nontemporal_load(b + (size_t)8 * vh + h);
-        f2v f = __builtin_convertvector(__builtin_bit_cast(h2v, wd), f2v);
-        w[8] = {f.x, f.y};
     }
 };
 

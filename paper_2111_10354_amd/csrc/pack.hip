@@ -18,38 +18,26 @@ __device__ __forceinline__ int64_t lex_of(const Geom &g, int x, int y, int z, in
     return x + (int64_t)g.L[0] * (y + (int64_t)g.L[1] * (z + (int64_t)g.L[2] * t));
 }
 
+// Write the 9 complex entries of slot k of site h into the tiled group layout.
 template <int F>
-__device__ void store_slot(void *dst, int vh, int k, int h, const cx<double> w[9]);
-
-template <>
-__device__ void store_slot<F64>(void *dst, int vh, int k, int h, const cx<double> w[9]) {
-    d2v *b = (d2v *)dst + (size_t)k * 9 * vh + h;
-    for (int e = 0; e < 9; ++e) b[(size_t)e * vh] = d2v{w[e].re, w[e].im};
-}
-
-template <>
-__device__ void store_slot<F32>(void *dst, int vh, int k, int h, const cx<double> w[9]) {
-    float *b = (float *)dst + (size_t)k * 18 * vh;
-    for (int q = 0; q < 4; ++q)
-        ((f4v *)(b + (size_t)q * 4 * vh))[h] =
-            f4v{(float)w[2 * q].re, (float)w[2 * q].im, (float)w[2 * q + 1].re, (float)w[2 * q + 1].im};
-    ((f2v *)(b + (size_t)16 * vh))[h] = f2v{(float)w[8].re, (float)w[8].im};
-}
-
-__device__ __forceinline__ unsigned int pack_h2(cx<double> v) {
-    // double -> float -> half: the float step is exact for entries of links
-    // (|v| < 2^14, far inside float range) up to float rounding, then RNE.
-    h2v hv = __builtin_convertvector((f2v{(float)v.re, (float)v.im}), h2v);
-    return __builtin_bit_cast(unsigned int, hv);
-}
-
-template <>
-__device__ void store_slot<H16>(void *dst, int vh, int k, int h, const cx<double> w[9]) {
-    unsigned int *b = (unsigned int *)dst + (size_t)k * 9 * vh;
-    for (int q = 0; q < 2; ++q)
-        ((u4v *)(b + (size_t)q * 4 * vh))[h] =
-            u4v{pack_h2(w[4 * q]), pack_h2(w[4 * q + 1]), pack_h2(w[4 * q + 2]), pack_h2(w[4 * q + 3])};
-    b[(size_t)8 * vh + h] = pack_h2(w[8]);
+__device__ void store_slot(void *dst, int k, int h, const cx<double> w[9]) {
+    constexpr int G = LinkGroup<F>::G;
+    constexpr int NG = 16 / G;
+    constexpr int CSIZE = 144 / (9 * G);  // bytes per complex entry: 16, 8, 4
+    const int gi = k / G, sl = k % G;
+    char *rec = (char *)dst + ((size_t)((h >> 6) * NG + gi) * 9) * 1024 + (size_t)(h & 63) * 16;
+    for (int c = 0; c < 9; ++c) {
+        const int off = (sl * 9 + c) * CSIZE;
+        char *q = rec + (size_t)(off >> 4) * 1024 + (off & 15);
+        if constexpr (F == F64) {
+            *(d2v *)q = d2v{w[c].re, w[c].im};
+        } else if constexpr (F == F32) {
+            *(f2v *)q = f2v{(float)w[c].re, (float)w[c].im};
+        } else {
+            // double -> float -> half, round to nearest even at each step
+            *(h2v *)q = __builtin_convertvector((f2v{(float)w[c].re, (float)w[c].im}), h2v);
+        }
+    }
 }
 
 template <int F>
@@ -77,7 +65,7 @@ __global__ __launch_bounds__(256) void k_pack_links(Geom g, const double *__rest
             }
             m = fmaxf(m, fmaxf(fabsf((float)w[3 * a + b].re), fabsf((float)w[3 * a + b].im)));
         }
-    store_slot<F>(dst, g.vh, k, h, w);
+    store_slot<F>(dst, k, h, w);
     if (maxabs_bits) atomicMax(maxabs_bits, __float_as_uint(m));  // m >= 0: bit order = value order
 }
 

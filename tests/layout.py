@@ -35,16 +35,23 @@ def from_cb(dims, cb: np.ndarray, parity: int) -> np.ndarray:
 
 def encode(cb: np.ndarray, prec: str) -> np.ndarray:
     """[3, Vh] complex128 -> raw bytes (uint8) of one library spinor buffer."""
+    vh = cb.shape[1]
     if prec == "fp64":
         return np.ascontiguousarray(cb.astype(np.complex128)).view(np.uint8).ravel()
     if prec == "fp32":
-        return np.ascontiguousarray(cb.astype(np.complex64)).view(np.uint8).ravel()
+        c = cb.astype(np.complex64)
+        plane_a = np.ascontiguousarray(c[:2].T)  # [Vh, 2] complex = (re0, im0, re1, im1)
+        plane_b = np.ascontiguousarray(c[2])     # [Vh] complex
+        return np.concatenate([plane_a.view(np.uint8).ravel(), plane_b.view(np.uint8).ravel()])
     if prec == "fp16s":
-        re = np.stack([cb.real, cb.imag], axis=-1)  # [3, Vh, 2]
-        scale = np.abs(re).max(axis=(0, 2)).astype(np.float32)  # per site
+        re = np.stack([cb.real, cb.imag], axis=-1).transpose(1, 0, 2).reshape(vh, 6)  # per site
+        scale = np.abs(re).max(axis=1).astype(np.float32)
         inv = np.where(scale > 0, 1.0 / scale.astype(np.float64), 0.0)
-        halves = (re * inv[None, :, None]).astype(np.float16)
-        return np.concatenate([halves.view(np.uint8).ravel(), scale.view(np.uint8).ravel()])
+        halves = (re * inv[:, None]).astype(np.float16)
+        rec = np.zeros((vh, 16), np.uint8)
+        rec[:, :12] = halves.view(np.uint8).reshape(vh, 12)
+        rec[:, 12:] = scale.view(np.uint8).reshape(vh, 4)
+        return rec.ravel()
     raise ValueError(prec)
 
 
@@ -54,12 +61,15 @@ def decode(raw: np.ndarray, vh: int, prec: str) -> np.ndarray:
     if prec == "fp64":
         return raw.view(np.complex128).reshape(3, vh).copy()
     if prec == "fp32":
-        return raw.view(np.complex64).reshape(3, vh).astype(np.complex128)
+        a = raw[: 16 * vh].view(np.complex64).reshape(vh, 2)
+        b = raw[16 * vh: 24 * vh].view(np.complex64)
+        return np.stack([a[:, 0], a[:, 1], b]).astype(np.complex128)
     if prec == "fp16s":
-        halves = raw[: 12 * vh].view(np.float16).reshape(3, vh, 2).astype(np.float64)
-        scale = raw[12 * vh: 16 * vh].view(np.float32).astype(np.float64)
-        v = halves * scale[None, :, None]
-        return v[..., 0] + 1j * v[..., 1]
+        rec = raw[: 16 * vh].reshape(vh, 16)
+        halves = np.ascontiguousarray(rec[:, :12]).view(np.float16).reshape(vh, 3, 2).astype(np.float64)
+        scale = np.ascontiguousarray(rec[:, 12:]).view(np.float32).reshape(vh).astype(np.float64)
+        v = halves * scale[:, None, None]
+        return (v[..., 0] + 1j * v[..., 1]).T.copy()
     raise ValueError(prec)
 
 

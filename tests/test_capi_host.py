@@ -107,3 +107,24 @@ def test_layout_helpers_roundtrip():
         err = np.abs(back - cb)
         scale = np.maximum(np.abs(cb.real), np.abs(cb.imag)).max(axis=0)
         assert np.all(err <= tol * scale[None, :] * 1.5 + 1e-300)
+
+
+def test_misaligned_spinors_rejected_before_any_gpu_work():
+    from paper_2111_10354_amd import hisq
+    fake_handle = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    rc = hisq.LIB.hisq_dslash_eo(fake_handle, 0, 1, C.c_void_p(0x10008), C.c_void_p(0x20000), None)
+    assert rc == hisq.ERR_INVALID and "aligned" in hisq.last_error()
+
+
+def test_no_bit_cast_of_vector_elements_in_device_code():
+    """hipcc (ROCm 7.2) compiles __builtin_bit_cast(T, v.w) / (T, v[i]) of an
+    ext_vector element as if it read element 0; the kernels bind the element to
+    a scalar first.  Guard against the pattern coming back."""
+    import glob
+    pat = re.compile(r"__builtin_bit_cast\(\s*[\w ]+,\s*[\w]+(\.[xyzw]\b|\[)")
+    bad = []
+    for path in glob.glob(os.path.join(ROOT, "paper_2111_10354_amd", "csrc", "*")):
+        for i, line in enumerate(open(path), 1):
+            if pat.search(line):
+                bad.append(f"{os.path.basename(path)}:{i}: {line.strip()}")
+    assert not bad, bad
