@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--only-fp32", action="store_true", help="time only the headline kernel")
+    ap.add_argument("--tune-cache", type=str, default=os.path.join(ROOT, "paper_2111_10354_amd", "tuning",
+                                                                  "gfx950.jsonl"),
+                    help="autotuner cache (JSON lines); shapes found there are used without timing")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 48^3x12 multi-RHS sweep")
     ap.add_argument("--fields-cache", type=str, default=None,
                     help="directory to save / reuse the generated link fields (profiling re-runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -141,6 +145,13 @@ def main():
     del fd, ld
     torch.cuda.empty_cache()
     log(f"gauge packed: {g.device_bytes() / 2**30:.1f} GiB of link copies")
+    tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
+    t1 = time.time()
+    for p in precs:
+        for n in ((1,) if args.only_fp32 else (1, cfg["nrhs"])):
+            hisq.autotune(g, p, n, tune)
+    log(f"autotune ({'cache ' + tune if tune else 'no cache'}): {time.time() - t1:.1f}s; "
+        f"FP32 1-RHS shape {hisq.dslash_shape(g, 'fp32', 1, 0)}")
 
     cb, odd_sites = cb_gather(dims, chi, 1)
     even_sites = cb_gather(dims, chi, 0)[1]
@@ -197,6 +208,14 @@ def main():
             v["gflops"] = FLOP_PER_SITE * vh * (4 if "x4" in k else 1) / (v["ms"] * 1e-3) / 1e9
             v["frac_hbm_peak"] = v["gbs"] / HBM_PEAK_GBS
 
+    shape = hisq.dslash_shape(g, "fp32", 1, 0)
+    sweep = None
+    if not (args.quick or args.no_sweep or args.only_fp32):
+        del bufs
+        g.close()
+        torch.cuda.empty_cache()
+        sweep = run_mrhs_sweep(hisq, torch, tune)
+
     # ---- CPU baseline: the FP64 oracle's Dslash on this lattice, host cores
     cpu = None
     if not (args.quick or args.no_cpu):
@@ -245,8 +264,43 @@ def main():
         "variants": variants,
         "cg": cg,
     }
+    result["config"]["launch_shape"] = {"rhs_tile": shape[0], "block": shape[1], "tile_order": shape[2]}
+    result["mrhs_sweep"] = sweep
     g.close()
     print(json.dumps(result), flush=True)
+
+
+def run_mrhs_sweep(hisq, torch, tune):
+    """Multi-RHS Dslash on 48^3 x 12 (FP32 and FP16S): time per launch and per RHS
+    for N = 1, 2, 4, 8, 16 with autotuned shapes."""
+    import synth
+    c = synth.CONFIGS["c3"]
+    dims = c["dims"]
+    vh = synth.volume(dims) // 2
+    log(f"multi-RHS sweep {dims}: generating fields")
+    F, L = synth.hisq_links(dims, synth.CFG_IDS["c3"], c["eps"])
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp32", "fp16s"))
+    del F, L
+    srcs = synth.gaussian_source(dims, synth.CFG_IDS["c3"], 16, parity=1)
+    out = {"workload": f"{'x'.join(map(str, dims))} single-parity Dslash, N right-hand sides", "fp32": {},
+           "fp16s": {}}
+    for p in ("fp32", "fp16s"):
+        raw = np.concatenate([encode(cb_gather(dims, s, 1)[0], p) for s in srcs])
+        i16 = torch.from_numpy(raw).cuda()
+        o16 = torch.empty_like(i16)
+        link = {"fp32": 1152, "fp16s": 576}[p]
+        spin = {"fp32": 24, "fp16s": 16}[p]
+        for n in (1, 2, 4, 8, 16):
+            hisq.autotune(g, p, n, tune)
+            nb = hisq.spinor_bytes(p, vh) * n
+            ms = time_launches(lambda: hisq.dslash_multi_rhs(g, 0, p, n, i16[:nb], o16[:nb]), 20, 3)
+            gbs = vh * (link + 2 * spin * n) / (ms * 1e-3) / 1e9
+            out[p][str(n)] = {"ms": round(ms, 4), "ms_per_rhs": round(ms / n, 4), "gbs": round(gbs, 1),
+                              "gflops": round(1146 * vh * n / (ms * 1e-3) / 1e9, 1),
+                              "shape": list(hisq.dslash_shape(g, p, n, 0))}
+            log(f"sweep {p} N={n}: {ms:.3f} ms ({ms / n:.3f} ms/RHS), {gbs:.0f} GB/s")
+    g.close()
+    return out
 
 
 def run_cg(hisq, torch):

@@ -137,6 +137,28 @@ int hisq_dslash_eo(hisq_gauge_t g, int out_parity, int prec, const void *in, voi
 int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in,
                           void *out, const double *diag, const void *y, void *stream);
 
+/*
+ * Autotune the Dslash launch shape (RHS tile per thread, block size, order in
+ * which the 64-site tiles are processed) for the kernels a solve in `prec`
+ * with `nrhs` right-hand sides launches: plain and epilogue Dslash in `prec`
+ * and, if FP64 links are packed, the FP64 kernels of the reliable updates.
+ * Each candidate must write bit-identical output to the default shape before
+ * it is timed (HIP events, the handle's own links, synthetic inputs).
+ *   cache_path  NULL, or a file of JSON lines {"key", "tile", "block",
+ *               "order", "ms"} keyed by GPU architecture, formats, lattice and
+ *               nrhs: a key found there is installed without timing, a new
+ *               result is appended.
+ * Installed shapes apply to later Dslash calls and solves on this handle.
+ * Synchronous.  Errors: -1 bad arguments (nrhs outside 1..64), -4 precision
+ * not packed.
+ */
+int hisq_autotune(hisq_gauge_t g, int prec, int nrhs, const char *cache_path, void *stream);
+
+/* Launch shape in use for (prec, nrhs, epilogue): epilogue 0 = plain Dslash,
+ * 1 = diag*y - D in with output in prec, 2 = the solver's form (FP16S input
+ * with FP32 output).  out[0] = RHS tile, out[1] = block size, out[2] = order. */
+int hisq_dslash_shape(hisq_gauge_t g, int prec, int nrhs, int epilogue, int out[3]);
+
 /* Solver controls (host struct).  Zero-initialise and set what you need;
  * hisq_solver_params_default() fills the defaults noted below. */
 typedef struct {

@@ -249,6 +249,40 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }
 
+int hisq_autotune(hisq_gauge_t g, int prec, int nrhs, const char *cache_path, void *stream) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
+    if (nrhs < 1 || nrhs > 64) return fail(HISQ_ERR_INVALID, "nrhs must be in 1..64");
+    if (!g->links[prec][0].p) return fail(HISQ_ERR_UNSUPPORTED, "links of this precision were not packed");
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g->mu);
+    const int fq = prec == H16 ? F32 : prec;
+    struct Job { int fl, fi, fo; bool epi; };
+    std::vector<Job> jobs = {{prec, prec, prec, false}, {prec, prec, fq, true}};
+    if (fq != prec) jobs.push_back({prec, prec, prec, true});
+    if (prec != F64 && g->links[F64][0].p) {  // FP64 kernels of the reliable updates
+        jobs.push_back({F64, F64, F64, false});
+        jobs.push_back({F64, F64, F64, true});
+    }
+    for (const Job &j : jobs)
+        if ((rc = tune_dslash(g, j.fl, j.fi, j.fo, nrhs, j.epi, cache_path, s, nullptr, nullptr))) return rc;
+    return HISQ_OK;
+}
+
+int hisq_dslash_shape(hisq_gauge_t g, int prec, int nrhs, int epilogue, int out[3]) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (!valid_prec(prec) || nrhs < 1 || epilogue < 0 || epilogue > 2 || !out)
+        return fail(HISQ_ERR_INVALID, "bad arguments");
+    const int fo = (epilogue == 2 && prec == H16) ? F32 : prec;
+    const DslashShape sh = pick_shape(g, prec, prec, fo, nrhs, epilogue != 0);
+    out[0] = sh.tile;
+    out[1] = sh.block;
+    out[2] = sh.order;
+    return HISQ_OK;
+}
+
 int hisq_precond_apply(hisq_gauge_t g, hisq_nn_t net, const void *in, void *out, void *stream) {
     int rc = check_handle(g);
     if (rc) return rc;

@@ -40,18 +40,33 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Processing order of the 64-site tiles.  order 0: memory order (x, y, z, t).
+// order 1: (z, t) planes with t fastest, which brings the time-direction
+// neighbours 16x closer in processing order (a win once several RHS make the
+// gathered spinors a large share of the traffic).  Needs whole tiles per plane.
+__device__ __forceinline__ int site_of_thread(const Geom &g, int i, int order) {
+    // grid tail: keep it out of range (the permutation below would map an
+    // index past the last tile back onto a valid one)
+    if (order == 0 || i >= g.vh) return i;
+    const int tpp = (g.lxh * g.L[1]) >> 6;  // tiles per (z, t) plane
+    const int wt = i >> 6;
+    const int q = wt / tpp, p = wt - q * tpp;
+    const int z = q / g.L[3], t = q - z * g.L[3];
+    return ((t * g.L[2] + z) * tpp + p) * 64 + (i & 63);
+}
+
 template <int LF, int SI, int SO, int TILE, bool EPI>
 __global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Spinor<SI> in,
                                                      Spinor<SO> out, Spinor<SI> y,
                                                      const double *__restrict__ diag,
                                                      double *__restrict__ partials,
                                                      const CgState *__restrict__ skip, int parity,
-                                                     int nrhs) {
+                                                     int nrhs, int order) {
     typedef typename RealOf<LF>::T R;
     constexpr int G = LinkGroup<LF>::G;
     const int nb = gridDim.x;
     const int blk = blockIdx.x;
-    const int h = blk * blockDim.x + threadIdx.x;
+    const int h = site_of_thread(g, blk * blockDim.x + threadIdx.x, order);
     const int r0 = blockIdx.y * TILE;
     if (skip) {
         bool idle = true;
@@ -154,7 +169,7 @@ static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
     Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);
     hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI>), grid, block, 0, s, g, L, in, out, y,
-                       a.diag, a.partials, a.skip, a.parity, a.nrhs);
+                       a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
 }
 
 template <int LF, int SI, int SO, bool EPI>
@@ -178,9 +193,17 @@ static int launch_epi(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     return a.diag ? launch_tile<LF, SI, SO, true>(g, a, s) : launch_tile<LF, SI, SO, false>(g, a, s);
 }
 
+bool order_supported(const Geom &g, int order) {
+    return order == 0 || (order == 1 && g.vh % 64 == 0 && (g.lxh * g.L[1]) % 64 == 0);
+}
+
 int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     if (a.block != 64 && a.block != 128 && a.block != 256) {
         set_error("dslash: block size must be 64, 128 or 256");
+        return HISQ_ERR_INVALID;
+    }
+    if (!order_supported(g, a.order)) {
+        set_error("dslash: traversal order not supported for this lattice");
         return HISQ_ERR_INVALID;
     }
     int rc = -1;

@@ -87,6 +87,7 @@ int gauge_dslash(hisq_gauge_s *g, int out_parity, int fl, int fi, int fo, int nr
     a.fmt_out = fo;
     a.tile = sh.tile;
     a.block = sh.block;
+    a.order = sh.order;
     return launch_dslash(g->geom, a, s);
 }
 

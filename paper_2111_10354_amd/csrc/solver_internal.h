@@ -72,6 +72,7 @@ struct DevBuf {
 struct DslashShape {
     int tile = 1;
     int block = 256;
+    int order = 0;
 };
 
 // Buffers, device state and the captured iteration graph of one solver shape.
@@ -121,6 +122,10 @@ int gauge_dslash(hisq_gauge_s *g, int out_parity, int fmt_links, int fmt_in, int
                  const CgState *skip, hipStream_t s);
 
 int nb_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int n, bool epi);
+
+// Time the candidate launch shapes (or read them from `cache`) and install the best.
+int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, const char *cache, hipStream_t s,
+                DslashShape *chosen, double *chosen_ms);
 size_t dslash_algorithmic_bytes(int fmt_links, int fmt_in, int fmt_out, int64_t vh, int nrhs, bool epi);
 
 int cg_solve(hisq_gauge_s *g, double mass, int nrhs, const double *b, double *x, const double *sigma,

@@ -66,6 +66,8 @@ def _load():
         "hisq_multishift_cg": (C.c_int, [vp, C.c_double, C.c_int, dp, vp, vp, C.POINTER(SolverParams),
                                          C.POINTER(SolverStats), vp]),
         "hisq_precond_apply": (C.c_int, [vp, vp, vp, vp, vp]),
+        "hisq_autotune": (C.c_int, [vp, C.c_int, C.c_int, C.c_char_p, vp]),
+        "hisq_dslash_shape": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -79,7 +81,8 @@ LIB = _load()
 # C ABI entry points declared in include/hisq.h (checked by the test-suite).
 EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_create",
            "hisq_gauge_destroy", "hisq_gauge_device_bytes", "hisq_dslash_eo", "hisq_dslash_multi_rhs",
-           "hisq_solver_params_default", "hisq_cg_solve", "hisq_multishift_cg", "hisq_precond_apply")
+           "hisq_solver_params_default", "hisq_cg_solve", "hisq_multishift_cg", "hisq_precond_apply",
+           "hisq_autotune", "hisq_dslash_shape")
 
 
 def last_error() -> str:
@@ -208,6 +211,19 @@ def multishift_cg(g: Gauge, mass: float, shifts, b, x, params: SolverParams | No
                                 C.byref(params) if params is not None else None, st, _stream(stream))
     _check(rc, allow_soft=True)
     return rc, [s.as_dict() for s in st]
+
+
+def autotune(g: Gauge, prec, nrhs: int, cache_path: str | None = None, stream=None):
+    """Time and install the best Dslash launch shapes for solves in `prec` with `nrhs` RHS."""
+    _check(LIB.hisq_autotune(g.handle, _prec(prec), int(nrhs),
+                             cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def dslash_shape(g: Gauge, prec, nrhs: int, epilogue: int = 0):
+    """(tile, block, order) currently used for this Dslash form."""
+    out = (C.c_int * 3)()
+    _check(LIB.hisq_dslash_shape(g.handle, _prec(prec), int(nrhs), int(epilogue), out))
+    return tuple(out)
 
 
 def precond_apply(g: Gauge, net, inp, out, stream=None):
