@@ -221,10 +221,48 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
  *                                            + Wb_mu,ab U_mu(x-mu)^+ psi_b(x-mu) ) ]
  * on the full lattice (the even input embedded with zeros on odd sites, the
  * output projected back to even sites), channel counts 1 -> C -> ... -> 1.
- *   in, out  device FP32 spinors [3][Vh] (even parity)
- * Errors: -1 bad arguments, -4 the handle was created without thin links.
+ *   in, out  device FP32 spinors (public FP32 layout, even parity)
+ * The layer weights are complex; the channel mixing runs as a BF16 matrix-core
+ * product with FP32 accumulation, the parallel transport in FP32.
+ * Errors: -1 bad arguments, -4 the handle has no thin links.
  */
 int hisq_precond_apply(hisq_gauge_t g, hisq_nn_t net, const void *in, void *out, void *stream);
+
+/* Thin links for the network: device, complex double [V][4][3][3] in the same
+ * canonical layout as the fat links, phases and boundary signs folded in.
+ * Packed to FP32 inside the handle; only read during the call. */
+int hisq_gauge_set_thin(hisq_gauge_t g, const double *thin, void *stream);
+
+/*
+ * Create a network with `nlayers` layers and channel counts channels[0..nlayers]
+ * (first and last 1, the others 1, 2, 4 or 8).  Weights: host complex double,
+ * layer after layer, each [9][C_out][C_in] with path index 0 = identity,
+ * 1 + mu = forward hop (U_mu(x) psi(x+mu)), 5 + mu = backward hop
+ * (U_mu(x-mu)^+ psi(x-mu)); NULL = all zero.  The network owns its weights,
+ * Adam state and activation buffers (sized for the handle's lattice).
+ */
+int hisq_nn_create(hisq_nn_t *out, hisq_gauge_t g, int nlayers, const int *channels, const double *weights,
+                   void *stream);
+int hisq_nn_destroy(hisq_nn_t net);
+/* Number of complex weights (the length of the arrays below, in complex numbers). */
+int hisq_nn_num_weights(hisq_nn_t net, size_t *n_complex);
+/* Copy the weights to / from a host array of 2 * n_complex doubles. */
+int hisq_nn_get_weights(hisq_nn_t net, double *weights, void *stream);
+int hisq_nn_set_weights(hisq_nn_t net, const double *weights, void *stream);
+
+/*
+ * Loss and gradient over a batch of pairs (A v_i, v_i), i < batch:
+ *   L = (1/batch) sum_i |N(A v_i) - v_i|^2 / |v_i|^2
+ * av, v: device FP32 spinors [batch][one buffer] (even parity).  *loss gets L;
+ * grad (host, 2 * n_complex doubles, or NULL) gets dL/dRe W + i dL/dIm W in the
+ * weight layout.  Synchronous.
+ */
+int hisq_nn_loss_grad(hisq_nn_t net, int batch, const void *av, const void *v, double *loss, double *grad,
+                      void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on the
+ * gradient of the batch; *loss gets the loss before the step.  Synchronous. */
+int hisq_nn_train_step(hisq_nn_t net, int batch, const void *av, const void *v, double lr, double *loss,
+                       void *stream);
 
 #ifdef __cplusplus
 }

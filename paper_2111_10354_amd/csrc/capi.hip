@@ -283,12 +283,4 @@ int hisq_dslash_shape(hisq_gauge_t g, int prec, int nrhs, int epilogue, int out[
     return HISQ_OK;
 }
 
-int hisq_precond_apply(hisq_gauge_t g, hisq_nn_t net, const void *in, void *out, void *stream) {
-    int rc = check_handle(g);
-    if (rc) return rc;
-    if (!net || !in || !out) return fail(HISQ_ERR_INVALID, "net, in and out are required");
-    (void)stream;
-    return fail(HISQ_ERR_UNSUPPORTED, "the preconditioner network is not available in this build");
-}
-
 }  // extern "C"

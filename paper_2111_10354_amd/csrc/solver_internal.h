@@ -104,6 +104,7 @@ struct hisq_gauge_s {
     int device = 0;
     hisq::DevBuf links[3][2];  // [format][output parity]
     hisq::DevBuf diag_buf;     // epilogue coefficients for hisq_dslash_multi_rhs
+    hisq::DevBuf thin;         // thin links (FP32) for the preconditioner network
     hipStream_t capture_stream = nullptr;
     std::mutex mu;
     // autotuned shapes keyed by (links fmt, in fmt, out fmt, nrhs, epilogue)

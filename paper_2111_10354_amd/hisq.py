@@ -67,6 +67,14 @@ def _load():
                                          C.POINTER(SolverStats), vp]),
         "hisq_precond_apply": (C.c_int, [vp, vp, vp, vp, vp]),
         "hisq_autotune": (C.c_int, [vp, C.c_int, C.c_int, C.c_char_p, vp]),
+        "hisq_gauge_set_thin": (C.c_int, [vp, vp, vp]),
+        "hisq_nn_create": (C.c_int, [C.POINTER(vp), vp, C.c_int, ip, dp, vp]),
+        "hisq_nn_destroy": (C.c_int, [vp]),
+        "hisq_nn_num_weights": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "hisq_nn_get_weights": (C.c_int, [vp, dp, vp]),
+        "hisq_nn_set_weights": (C.c_int, [vp, dp, vp]),
+        "hisq_nn_loss_grad": (C.c_int, [vp, C.c_int, vp, vp, dp, dp, vp]),
+        "hisq_nn_train_step": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, dp, vp]),
         "hisq_dslash_shape": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
@@ -82,7 +90,9 @@ LIB = _load()
 EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_create",
            "hisq_gauge_destroy", "hisq_gauge_device_bytes", "hisq_dslash_eo", "hisq_dslash_multi_rhs",
            "hisq_solver_params_default", "hisq_cg_solve", "hisq_multishift_cg", "hisq_precond_apply",
-           "hisq_autotune", "hisq_dslash_shape")
+           "hisq_autotune", "hisq_dslash_shape", "hisq_gauge_set_thin", "hisq_nn_create", "hisq_nn_destroy",
+           "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
+           "hisq_nn_train_step")
 
 
 def last_error() -> str:
@@ -226,5 +236,69 @@ def dslash_shape(g: Gauge, prec, nrhs: int, epilogue: int = 0):
     return tuple(out)
 
 
-def precond_apply(g: Gauge, net, inp, out, stream=None):
-    _check(LIB.hisq_precond_apply(g.handle, net, _ptr(inp), _ptr(out), _stream(stream)))
+def gauge_set_thin(g: Gauge, thin: torch.Tensor, stream=None):
+    """Thin links (complex128 [V,4,3,3] device tensor, phases folded) for the network."""
+    _check(LIB.hisq_gauge_set_thin(g.handle, _ptr(thin), _stream(stream)))
+
+
+class Net:
+    """Preconditioner network (see hisq_nn_create); weights as a flat complex128 numpy array."""
+
+    def __init__(self, g: Gauge, channels, weights=None, stream=None):
+        import numpy as np
+        self.channels = tuple(int(c) for c in channels)
+        nl = len(self.channels) - 1
+        ch = (C.c_int * (nl + 1))(*self.channels)
+        w = None
+        if weights is not None:
+            wa = np.ascontiguousarray(np.asarray(weights, np.complex128).ravel())
+            w = wa.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        _check(LIB.hisq_nn_create(C.byref(h), g.handle, nl, ch, w, _stream(stream)))
+        self.handle = h
+        n = C.c_size_t()
+        _check(LIB.hisq_nn_num_weights(h, C.byref(n)))
+        self.n = n.value
+
+    def get_weights(self, stream=None):
+        import numpy as np
+        out = np.zeros(self.n, np.complex128)
+        _check(LIB.hisq_nn_get_weights(self.handle, out.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                                       _stream(stream)))
+        return out
+
+    def set_weights(self, weights, stream=None):
+        import numpy as np
+        wa = np.ascontiguousarray(np.asarray(weights, np.complex128).ravel())
+        assert wa.size == self.n
+        _check(LIB.hisq_nn_set_weights(self.handle, wa.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                                       _stream(stream)))
+
+    def loss_grad(self, batch, av, v, want_grad=True, stream=None):
+        import numpy as np
+        loss = C.c_double()
+        grad = np.zeros(self.n, np.complex128) if want_grad else None
+        gp = grad.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)) if want_grad else None
+        _check(LIB.hisq_nn_loss_grad(self.handle, int(batch), _ptr(av), _ptr(v), C.byref(loss), gp, _stream(stream)))
+        return loss.value, grad
+
+    def train_step(self, batch, av, v, lr, stream=None):
+        loss = C.c_double()
+        _check(LIB.hisq_nn_train_step(self.handle, int(batch), _ptr(av), _ptr(v), float(lr), C.byref(loss),
+                                      _stream(stream)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            LIB.hisq_nn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def precond_apply(g: Gauge, net: Net, inp, out, stream=None):
+    _check(LIB.hisq_precond_apply(g.handle, net.handle, _ptr(inp), _ptr(out), _stream(stream)))
