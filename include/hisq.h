@@ -197,7 +197,17 @@ void hisq_solver_params_default(hisq_solver_params *p);
  *   p     host params (NULL = defaults); st host array of nrhs stats (or NULL).
  * nrhs > 1 runs nrhs independent CGs in lockstep sharing multi-RHS Dslash
  * launches.  Stops on the FP64 true residual.  Synchronous.
- * Returns the worst per-RHS status (0 if all converged).
+ * With p->precond set, each right-hand side is solved in turn by flexible CG
+ * (Notay, SIAM J. Sci. Comput. 22 (2000), FCG(1): the learned preconditioner
+ * beside the paper's solver family, which is an extension of it) with z = N(r) in FP32, complex step sizes and FP64 reliable updates every
+ * ru_period iterations, each restarting the direction from N(r); the network
+ * must belong to g and the handle needs FP64 and FP32 links plus thin links.
+ * A breakdown, or three reliable updates in a row that fail to halve the true
+ * residual, hands the solve to plain FP64 CG from the current x when
+ * p->fallback is set (status HISQ_CONVERGED_AFTER_FALLBACK on success); a
+ * mixed-precision solve that breaks down is finished the same way.
+ * Returns the worst per-RHS status in the order 0 < CONVERGED_AFTER_FALLBACK
+ * < NOT_CONVERGED < BREAKDOWN (0 if all converged).
  */
 int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double *x,
                   const hisq_solver_params *p, hisq_solver_stats *st, void *stream);

@@ -129,3 +129,54 @@ def init_weights(channels, rng, scale_identity=1.0, noise=1e-3):
         W[0, 0, 0] += scale_identity
         ws.append(W)
     return ws
+
+
+# --------------------------------------------------------------------------
+# The function class of a two- or three-layer network.  Every path through
+# three nearest-neighbour layers has 0, 1, 2 or 3 hops; from an even input
+# only the 0- and 2-hop paths end on even sites, and a hop followed by its
+# own reverse is the identity (unitary thin links).  So N restricted to even
+# sites lies in the span of the identity and the 56 distinct transported
+# two-hop paths T_b T_a, and the best loss any such network can reach on a
+# set of pairs is a linear least-squares problem over those 57 features.
+
+def two_hop_paths():
+    """(first, second) path indices of the 56 distinct two-hop paths."""
+    out = []
+    for a in range(1, NPATH):
+        for b in range(1, NPATH):
+            if b == adjoint_path(a):
+                continue
+            out.append((a, b))
+    return out
+
+
+def two_hop_features(dims, U, r):
+    """[57, V, 3]: r and T_b T_a r for every distinct two-hop path (a then b)."""
+    first = {a: transport(dims, U, r, a) for a in range(1, NPATH)}
+    feats = [r.copy()]
+    for a, b in two_hop_paths():
+        feats.append(transport(dims, U, first[a], b))
+    return np.stack(feats)
+
+
+def stencil_optimum(dims, U, pairs):
+    """Least loss over the even-site span of the 57 features:
+    min_c (1/B) sum_i |sum_k c_k f_k(A v_i) - v_i|^2 / |v_i|^2 (even sites).
+    Returns (loss, c, scalar_loss) where scalar_loss is the optimum of c I alone."""
+    em = even_mask(dims)
+    rows, rhs = [], []
+    for Av, v in pairs:
+        nv = np.sqrt(float(np.vdot(v, v).real))
+        f = two_hop_features(dims, U, Av)[:, em, :].reshape(57, -1)
+        rows.append(f.T / nv)
+        rhs.append(v[em].ravel() / nv)
+    M = np.concatenate(rows)
+    y = np.concatenate(rhs)
+    c, *_ = np.linalg.lstsq(M, y, rcond=None)
+    res = M @ c - y
+    B = len(pairs)
+    m0 = M[:, 0]
+    c0 = np.vdot(m0, y) / np.vdot(m0, m0)
+    r0 = m0 * c0 - y
+    return float(np.vdot(res, res).real) / B, c, float(np.vdot(r0, r0).real) / B

@@ -52,7 +52,6 @@ static int check_params(const hisq_solver_params &p) {
     if (p.max_iter < 1) return fail(HISQ_ERR_INVALID, "max_iter must be >= 1");
     if (!valid_prec(p.sloppy_prec)) return fail(HISQ_ERR_INVALID, "bad sloppy_prec");
     if (p.graph_chunk < 0 || p.graph_chunk > 4096) return fail(HISQ_ERR_INVALID, "graph_chunk out of range");
-    if (p.precond) return fail(HISQ_ERR_UNSUPPORTED, "preconditioned CG is not available in this build");
     return HISQ_OK;
 }
 
@@ -62,6 +61,7 @@ using namespace hisq;
 
 hisq_gauge_s::~hisq_gauge_s() {
     cg_ws.clear();
+    fcg_ws.reset();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
@@ -226,7 +226,19 @@ int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double
     if (b == x) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
     if ((rc = check_spinors(b, x))) return rc;
     std::lock_guard<std::mutex> lk(g->mu);
-    return cg_solve(g, mass, nrhs, b, x, nullptr, prm, st, (hipStream_t)stream);
+    if (prm.precond) {
+        // flexible CG: one right-hand side after another
+        const size_t sb = spinor_bytes(F64, g->geom.vh);
+        int worst = HISQ_OK;
+        for (int i = 0; i < nrhs; ++i) {
+            rc = fcg_solve(g, mass, (const double *)((const char *)b + sb * i), (double *)((char *)x + sb * i),
+                           prm, st ? st + i : nullptr, (hipStream_t)stream);
+            if (rc < 0) return rc;
+            if (status_severity(rc) > status_severity(worst)) worst = rc;
+        }
+        return worst;
+    }
+    return cg_solve_fallback(g, mass, nrhs, b, x, prm, st, (hipStream_t)stream);
 }
 
 int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *shifts, const double *b,
@@ -238,6 +250,7 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
     else hisq_solver_params_default(&prm);
     if ((rc = check_params(prm))) return rc;
     if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
+    if (prm.precond) return fail(HISQ_ERR_UNSUPPORTED, "multi-shift CG takes no preconditioner");
     if (nshift < 1 || nshift > 256 || !shifts)
         return fail(HISQ_ERR_INVALID, "1 <= nshift <= 256 and shifts are required");
     for (int k = 0; k < nshift; ++k)

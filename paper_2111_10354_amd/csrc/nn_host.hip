@@ -3,6 +3,7 @@
 // back-propagation through the adjoint layers, and Adam steps.
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 
 #include "nn_internal.h"
@@ -19,7 +20,9 @@ static NnGeom nn_geom(const hisq_gauge_s *g) {
 static size_t act_bytes(const NnGeom &G, int c) { return spinor_bytes(F32, G.V) * c; }
 
 int nn_create(hisq_nn_s **out, hisq_gauge_s *g, int nlayers, const int *ch, const double *weights, hipStream_t s) {
+    static std::atomic<unsigned long long> next_id{1};
     hisq_nn_s *n = new hisq_nn_s();
+    n->id = next_id++;
     n->gauge = g;
     n->nlayers = nlayers;
     n->ch.assign(ch, ch + nlayers + 1);

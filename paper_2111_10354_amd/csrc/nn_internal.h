@@ -43,4 +43,5 @@ struct hisq_nn_s {
     hisq::DevBuf out, gout, partial, scal, partd;
     int step = 0;
     bool amat_valid = false;
+    unsigned long long id = 0;        // unique per network created in this process
 };

@@ -321,4 +321,48 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     return worst;
 }
 
+int status_severity(int st) {
+    switch (st) {
+        case HISQ_OK: return 0;
+        case HISQ_CONVERGED_AFTER_FALLBACK: return 1;
+        case HISQ_NOT_CONVERGED: return 2;
+        default: return 3;
+    }
+}
+
+int cg_solve_fallback(hisq_gauge_s *g, double mass, int n, const double *b, double *x,
+                      const hisq_solver_params &prm, hisq_solver_stats *stats, hipStream_t s) {
+    std::vector<hisq_solver_stats> own(n);
+    hisq_solver_stats *st = stats ? stats : own.data();
+    int rc = cg_solve(g, mass, n, b, x, nullptr, prm, st, s);
+    if (rc <= 0 || prm.sloppy_prec == HISQ_PREC_FP64 || !prm.fallback) return rc;
+    // a mixed-precision breakdown, or a stop short of the iteration cap, is
+    // finished by plain FP64 CG from the current solution
+    const size_t sb = spinor_bytes(F64, g->geom.vh);
+    hisq_solver_params cp = prm;
+    cp.sloppy_prec = HISQ_PREC_FP64;
+    cp.warm_start = 1;
+    int worst = HISQ_OK;
+    for (int i = 0; i < n; ++i) {
+        hisq_solver_stats &o = st[i];
+        const bool redo = o.status == HISQ_BREAKDOWN || (o.status == HISQ_NOT_CONVERGED && o.iterations < prm.max_iter);
+        if (redo) {
+            hisq_solver_stats f;
+            std::memset(&f, 0, sizeof(f));
+            rc = cg_solve(g, mass, 1, (const double *)((const char *)b + sb * i), (double *)((char *)x + sb * i),
+                          nullptr, cp, &f, s);
+            if (rc < 0) return rc;
+            o.status = f.status == HISQ_OK ? HISQ_CONVERGED_AFTER_FALLBACK : f.status;
+            o.iterations += f.iterations;
+            o.reliable_updates += f.reliable_updates;
+            o.fallback_used = 1;
+            o.true_residual = f.true_residual;
+            o.wall_ms += f.wall_ms;
+            o.dslash_bytes += f.dslash_bytes;
+        }
+        if (status_severity(o.status) > status_severity(worst)) worst = o.status;
+    }
+    return worst;
+}
+
 }  // namespace hisq

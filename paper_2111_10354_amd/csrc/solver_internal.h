@@ -96,6 +96,21 @@ struct CgWorkspace {
     CgState *st() { return (CgState *)state.p; }
 };
 
+// Buffers, device state and the captured iteration graph of flexible CG.
+struct FcgWorkspace {
+    DevBuf b64, x64, r64, t64, ax64;
+    DevBuf xs, rs, ps, qs, zs, ts;
+    DevBuf part, part2, state, diag, scal;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long net_id = 0;  // network the graph was captured with
+    int chunk = 0;
+    FcgWorkspace() = default;
+    FcgWorkspace(const FcgWorkspace &) = delete;
+    FcgWorkspace &operator=(const FcgWorkspace &) = delete;
+    ~FcgWorkspace();
+};
+
 }  // namespace hisq
 
 struct hisq_gauge_s {
@@ -110,6 +125,7 @@ struct hisq_gauge_s {
     // autotuned shapes keyed by (links fmt, in fmt, out fmt, nrhs, epilogue)
     std::map<std::tuple<int, int, int, int, int>, hisq::DslashShape> shapes;
     std::map<std::tuple<int, int, int>, std::unique_ptr<hisq::CgWorkspace>> cg_ws;  // (n, fmt, chunk)
+    std::unique_ptr<hisq::FcgWorkspace> fcg_ws;
     ~hisq_gauge_s();
 };
 
@@ -131,6 +147,18 @@ size_t dslash_algorithmic_bytes(int fmt_links, int fmt_in, int fmt_out, int64_t 
 
 int cg_solve(hisq_gauge_s *g, double mass, int nrhs, const double *b, double *x, const double *sigma,
              const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);
+
+// Severity order of soft outcomes: OK < converged after fallback < not converged < breakdown.
+int status_severity(int status);
+
+// cg_solve, then plain FP64 CG from the current x for every RHS whose
+// mixed-precision solve broke down or stopped short of the iteration cap.
+int cg_solve_fallback(hisq_gauge_s *g, double mass, int n, const double *b, double *x,
+                      const hisq_solver_params &prm, hisq_solver_stats *stats, hipStream_t s);
+
+// Flexible CG for one right-hand side with z = N(r) (prm.precond set).
+int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hisq_solver_params &prm,
+              hisq_solver_stats *stats, hipStream_t s);
 
 int multishift_solve(hisq_gauge_s *g, double mass, int nshift, const double *shifts, const double *b,
                      double *x, const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);

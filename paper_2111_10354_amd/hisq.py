@@ -198,6 +198,8 @@ def solver_params(**kw) -> SolverParams:
     for k, v in kw.items():
         if k == "sloppy_prec":
             v = _prec(v)
+        if k == "precond" and isinstance(v, Net):
+            v = v.handle.value
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, v)

@@ -6,7 +6,10 @@
   links = thin links and no Naik term;
 * gauge covariance and linearity of the network;
 * the analytic gradient against central finite differences of the loss, on
-  the real and on the imaginary part of sampled weights of every layer.
+  the real and on the imaginary part of sampled weights of every layer;
+* the function class: a three-layer network's even-site output is fitted
+  exactly by the identity plus the 56 two-hop paths, so the least-squares
+  optimum over those features bounds the loss of every such network.
 """
 
 import numpy as np
@@ -98,3 +101,41 @@ def test_adjoint_paths_are_adjoints(small):
         lhs = np.vdot(y, nn.transport(dims, U, x, p))
         rhs = np.vdot(nn.transport(dims, U, y, nn.adjoint_path(p)), x)
         assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_three_layer_networks_span_two_hop_stencils(small):
+    """Any three-layer network restricted to even sites is a combination of the
+    identity and the 56 two-hop paths: fitting its outputs is exact."""
+    dims, U = small
+    rng = np.random.default_rng(11)
+    ws = nn.init_weights([1, 3, 2, 1], rng, scale_identity=0.7, noise=0.4)
+    pairs = []
+    for k in range(3):
+        w = _even(dims, 20 + k)
+        pairs.append((w, nn.forward(dims, U, ws, w)[0]))
+    loss, c, scalar = nn.stencil_optimum(dims, U, pairs)
+    assert loss < 1e-24, loss
+    assert scalar > 1e-3
+    # one layer reaches only the identity on even sites (a single hop lands on odd ones)
+    ws1 = nn.init_weights([1, 1], rng, scale_identity=0.7, noise=0.4)
+    w = _even(dims, 30)
+    out = nn.forward(dims, U, ws1, w)[0]
+    coef = np.vdot(w, out) / np.vdot(w, w)
+    assert np.linalg.norm(out - coef * w) < 1e-12 * np.linalg.norm(out)
+
+
+def test_stencil_optimum_bounds_any_network(small):
+    dims, U = small
+    F, L, _ = synth.hisq_links(dims, 99, 0.5, want_thin=True)
+    mass = 0.2
+    pairs = []
+    for k in range(3):
+        v = _even(dims, 40 + k)
+        pairs.append((oracle.normal_op(dims, F, L, mass, v), v))
+    best, c, scalar = nn.stencil_optimum(dims, U, pairs)
+    assert best <= scalar
+    rng = np.random.default_rng(5)
+    for noise in (0.0, 0.05, 0.3):
+        ws = nn.init_weights([1, 4, 4, 1], rng, scale_identity=0.1, noise=noise)
+        Lnet, _ = nn.loss_and_grad(dims, U, ws, pairs)
+        assert Lnet >= best * (1 - 1e-12)
