@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip CG and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-nn", action="store_true", help="skip the preconditioner network training and FCG")
     ap.add_argument("--only-fp32", action="store_true", help="time only the headline kernel")
     ap.add_argument("--tune-cache", type=str, default=os.path.join(ROOT, "paper_2111_10354_amd", "tuning",
                                                                   "gfx950.jsonl"),
@@ -239,6 +240,11 @@ def main():
     if not (args.quick or args.no_cg):
         cg = run_cg(hisq, torch)
 
+    # ---- network preconditioner on the 32^3 x 8, m = 0.005 workload
+    nnres = None
+    if not (args.quick or args.no_nn):
+        nnres = run_nn(hisq, torch)
+
     result = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -263,6 +269,7 @@ def main():
         "parity_sample_rel_l2": perr,
         "variants": variants,
         "cg": cg,
+        "nn_fcg": nnres,
     }
     result["config"]["launch_shape"] = {"rhs_tile": shape[0], "block": shape[1], "tile_order": shape[2]}
     result["mrhs_sweep"] = sweep
@@ -331,6 +338,94 @@ def run_cg(hisq, torch):
     best = min(("mixed_fp32", "mixed_fp16s"), key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
     out["chosen"] = best
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
+    g.close()
+    return out
+
+
+def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
+    """Train the 1 -> 8 -> 8 -> 1 network on (A v, v) pairs generated on the GPU from
+    this gauge field (v Gaussian from a seeded torch generator), then solve one
+    Gaussian RHS with plain FP64 CG, mixed FP32 CG and flexible CG with the
+    untrained (identity / 6) and the trained network."""
+    import synth
+    c = synth.CONFIGS["c4"]
+    dims, mass = c["dims"], c["mass"]
+    vh = synth.volume(dims) // 2
+    log(f"network workload {dims} m={mass}: generating fields")
+    F, L, U = synth.hisq_links(dims, synth.CFG_IDS["c4"], c["eps"], want_thin=True)
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32"))
+    hisq.gauge_set_thin(g, torch.from_numpy(np.ascontiguousarray(U)).cuda())
+    del F, L, U
+    diag = 4 * mass * mass
+    chans = (1, 8, 8, 1)
+    w0 = np.zeros(9 * (8 + 64 + 8), np.complex128)
+    w0[0] = 1.0 / (diag + 6.0)          # layer 1, identity path, channel 0
+    w0[9 * 8] = 1.0                     # layer 2, identity path, 0 -> 0
+    w0[9 * 8 + 9 * 64] = 1.0            # layer 3, identity path, 0 -> 0
+    ident = hisq.Net(g, chans, w0)
+    net = hisq.Net(g, chans, w0)
+    n6 = 6 * vh                          # floats per FP32 spinor
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2111_10354)
+    V = torch.randn(npairs * n6, generator=gen, device="cuda", dtype=torch.float32)
+    AV = torch.empty_like(V)
+    T = torch.empty(16 * n6, device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(0, npairs, 16):
+        k = min(16, npairs - i)
+        vv, aa = V[i * n6:(i + k) * n6], AV[i * n6:(i + k) * n6]
+        hisq.dslash_multi_rhs(g, 1, "fp32", k, vv, T[:k * n6])
+        hisq.dslash_multi_rhs(g, 0, "fp32", k, T[:k * n6], aa, diag=[diag] * k, y=vv)
+    torch.cuda.synchronize()
+    t_pairs = time.time() - t0
+    del T
+    l0 = net.loss_grad(batch, AV[:batch * n6], V[:batch * n6], want_grad=False)[0]
+    steps = epochs * (npairs // batch)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for s in range(steps):
+        i = s % (npairs // batch)
+        net.train_step(batch, AV[i * batch * n6:(i + 1) * batch * n6], V[i * batch * n6:(i + 1) * batch * n6], lr)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    l1 = net.loss_grad(batch, AV[:batch * n6], V[:batch * n6], want_grad=False)[0]
+    log(f"network: {npairs} pairs in {t_pairs:.2f} s, {steps} Adam steps in {t_train:.1f} s, "
+        f"loss {l0:.4f} -> {l1:.4f}")
+    del V, AV
+    torch.cuda.empty_cache()
+    # cost of one network pass against one FP32 application of A
+    r = torch.randn(n6, generator=gen, device="cuda", dtype=torch.float32)
+    z, t1 = torch.empty_like(r), torch.empty_like(r)
+    hisq.precond_apply(g, net, r, z)
+    ms_nn = time_launches(lambda: hisq.precond_apply(g, net, r, z), 20, 3)
+    ms_a = time_launches(lambda: (hisq.dslash_multi_rhs(g, 1, "fp32", 1, r, t1),
+                                  hisq.dslash_multi_rhs(g, 0, "fp32", 1, t1, z, diag=[diag], y=r)), 20, 3)
+    b = synth.gaussian_source(dims, synth.CFG_IDS["c4"], 1, parity=0)[0]
+    bd = torch.from_numpy(encode(cb_gather(dims, b, 0)[0], "fp64")).cuda()
+    out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, network 1-8-8-1 (BF16 MFMA mixing), "
+                       f"{npairs} (A v, v) pairs, batch {batch}, {epochs} epoch(s), 1 Gaussian RHS, tol 1e-10",
+           "pairs_seconds": round(t_pairs, 3), "train_seconds": round(t_train, 2), "train_steps": steps,
+           "loss_start": round(l0, 5), "loss_trained": round(l1, 5),
+           "ms_network_pass": round(ms_nn, 4), "ms_A_fp32": round(ms_a, 4), "solves": {}}
+    for name, kw in (("plain_fp64", {}), ("mixed_fp32", {"sloppy_prec": "fp32"}),
+                     ("fcg_untrained", {"precond": ident}), ("fcg_trained", {"precond": net})):
+        x = torch.zeros_like(bd)
+        hisq.cg_solve(g, mass, 1, bd, x, hisq.solver_params(max_iter=50, **kw))
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.time()
+        rc, st = hisq.cg_solve(g, mass, 1, bd, x, hisq.solver_params(**kw))
+        wall = time.time() - t1
+        out["solves"][name] = {"status": rc, "seconds": round(wall, 4), "iterations": st[0]["iterations"],
+                               "fallback_used": st[0]["fallback_used"], "true_residual": st[0]["true_residual"]}
+        log(f"{name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
+    sv = out["solves"]
+    out["iterations_trained_over_plain"] = round(sv["fcg_trained"]["iterations"] / sv["plain_fp64"]["iterations"], 4)
+    out["iterations_trained_over_untrained"] = round(sv["fcg_trained"]["iterations"] /
+                                                     sv["fcg_untrained"]["iterations"], 4)
+    ident.close()
+    net.close()
     g.close()
     return out
 
