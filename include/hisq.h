@@ -233,19 +233,22 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
  * output projected back to even sites), channel counts 1 -> C -> ... -> 1.
  *   in, out  device FP32 spinors (public FP32 layout, even parity)
  * The layer weights are complex; the channel mixing runs as a BF16 matrix-core
- * product with FP32 accumulation, the parallel transport in FP32.
+ * product with FP32 accumulation, the parallel transport in FP32 on FP16
+ * links, and hidden activations are stored in BF16.
  * Errors: -1 bad arguments, -4 the handle has no thin links.
  */
 int hisq_precond_apply(hisq_gauge_t g, hisq_nn_t net, const void *in, void *out, void *stream);
 
 /* Thin links for the network: device, complex double [V][4][3][3] in the same
  * canonical layout as the fat links, phases and boundary signs folded in.
- * Packed to FP32 inside the handle; only read during the call. */
+ * Packed to FP16 inside the handle (entries of unitary links are at most 1 in
+ * magnitude); only read during the call.  Synchronous.
+ * Errors: -1 if an entry is not finite or |entry| >= 32768. */
 int hisq_gauge_set_thin(hisq_gauge_t g, const double *thin, void *stream);
 
 /*
  * Create a network with `nlayers` layers and channel counts channels[0..nlayers]
- * (first and last 1, the others 1, 2, 4 or 8).  Weights: host complex double,
+ * (first and last 1, the others 1..8).  Weights: host complex double,
  * layer after layer, each [9][C_out][C_in] with path index 0 = identity,
  * 1 + mu = forward hop (U_mu(x) psi(x+mu)), 5 + mu = backward hop
  * (U_mu(x-mu)^+ psi(x-mu)); NULL = all zero.  The network owns its weights,

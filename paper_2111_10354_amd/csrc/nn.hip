@@ -1,24 +1,34 @@
 // Gauge-covariant preconditioner network: forward, backward and Adam kernels.
 //
-// Layer with CIN -> COUT complex channels on the full lattice:
+// Layer with C_in -> C_out complex channels (C <= 8) on the full lattice:
 //   y_a(x) = sum_b [ W0_ab psi_b(x) + sum_mu ( Wf_mu,ab U_mu(x) psi_b(x+mu)
 //                                            + Wb_mu,ab U_mu(x-mu)^+ psi_b(x-mu) ) ]
 // (linear, gauge covariant; the L-CNN construction of Favoni et al. 2022 used
 // as a solver preconditioner as in Lehner and Wettig 2023).
 //
-// One wavefront handles 16 sites = 48 (site, colour) columns:
-//  1. its four lane groups compute the 9 transported inputs T_p psi_b of every
-//     input channel in FP32 (lane group j owns the paths p = j, j+4, j+8) and
-//     write them to LDS as BF16;
-//  2. the channel mixing is a real GEMM  [Re y; Im y] (16 x 48) =
-//     [[Wr, -Wi], [Wi, Wr]] (16 x 2K) x [Re T; Im T] (2K x 48), K = 9 CIN, run
-//     on v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
-//  3. the 16 x 48 result is staged in LDS and written as FP32 activations.
-// The transposed layer needed by back-propagation is the same kernel with
-// weights W'_{p'} = W_p^H, p' the adjoint hop (forward and backward swap).
-// Weight gradients G(W_p[a][b]) = sum_{x,c} g_a(x)_c conj((T_p psi_b)(x)_c) use
-// the same MFMA with the (site, colour) dimension as the reduction, per-block
-// partials and a fixed-order final sum (deterministic).
+// Storage in HBM:
+//  * hidden activations and back-propagated gradients: BF16, always 8
+//    channels (unused ones hold zeros).  A site is six 16-byte units
+//    u = 2 colour + (0: re, 1: im), each holding channels 0..7, tiled by 64
+//    sites: unit u of site s at byte ((s / 64) * 6 + u) * 1024 + (s % 64) * 16.
+//  * network input and output: FP32 spinors of the public layout, even sites.
+//  * thin links: FP16, a 144-byte record per site (links mu = 0..3 of 9
+//    complex entries, entry k of link mu in 32-bit word 9 mu + k), tiled by 64
+//    sites like the activations, nine units per site.
+//
+// Kernel: a wavefront owns 32 sites, i.e. 96 (site, colour) columns, and
+// builds the layer as the real-block GEMM
+//   [Re y; Im y] (16 x 96) = A (16 x K) B (K x 96),  A = [[Wr, -Wi], [Wi, Wr]],
+// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  B is the transported
+// input, produced 32 K rows at a time (two paths x {re, im} x 8 channels) by
+// the wave's lanes in FP32 and staged in LDS as BF16: lane pair (site, half)
+// loads the neighbour's units and the link once per pair and each half
+// transports 4 of the 8 channels.  The result is staged in LDS and written
+// as whole 16-byte units.  The adjoint layer needed by back-propagation is
+// the same kernel with weights W'_{p'} = W_p^H, p' the adjoint hop.  Weight
+// gradients G(W_p[a][b]) = sum_{x,c} g_a(x)_c conj((T_p psi_b)(x)_c) use the
+// same MFMA with (site, colour, re/im) as the reduction, per-block partials
+// and a fixed-order final sum (deterministic).
 
 #include <algorithm>
 #include <cmath>
@@ -30,315 +40,518 @@
 namespace hisq {
 
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
 
-constexpr int NN_SITES = 16;             // sites per wavefront
-constexpr int NN_COLS = NN_SITES * 3;    // 48 MFMA columns
-constexpr int NN_WAVES = 2;              // wavefronts per block
+constexpr int NW_SITES = 32;                 // sites per wavefront
+constexpr int NW_COLS = 3 * NW_SITES;        // (site, colour) columns per wavefront
+constexpr int NN_WAVES = 2;                  // wavefronts per block
+constexpr int NB_SITES = NW_SITES * NN_WAVES;
+constexpr int BT_LD = 40;                    // bf16 per LDS column of B: 32 K rows + pad
+constexpr int GT_LD = 2 * NW_COLS + 8;       // bf16 per LDS row of the gradient operand
 
-__host__ __device__ constexpr int kpad(int cin) { return ((2 * 9 * cin + 31) / 32) * 32; }
+enum { IO_FULL = 0, IO_EVEN = 1 };
 
-// ------------------------------------------------------------------ geometry (full lattice)
+// K extent of the real-block weight matrix: 9 paths x {re, im} x 8 channels
+// padded to 160 for hidden inputs, 9 paths x {re, im} padded to 32 for the
+// one-channel even-site input.
+__host__ __device__ constexpr int kp_of(int inm) { return inm == IO_EVEN ? 32 : 160; }
+
+// ------------------------------------------------------------------ geometry (full lattice, lex order)
 struct Lex {
     int L[4];
     int V;
-    __device__ __forceinline__ void coords(int s, int c[4]) const {
-        c[0] = s % L[0];
-        s /= L[0];
-        c[1] = s % L[1];
-        s /= L[1];
-        c[2] = s % L[2];
-        c[3] = s / L[2];
-    }
-    __device__ __forceinline__ int lex(const int c[4]) const { return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3])); }
-    __device__ __forceinline__ int hop(int s, int mu, int d) const {
-        int c[4];
-        coords(s, c);
-        c[mu] = wrap(c[mu] + d, L[mu]);
-        return lex(c);
-    }
-    __device__ __forceinline__ int parity(int s) const {
-        int c[4];
-        coords(s, c);
-        return (c[0] + c[1] + c[2] + c[3]) & 1;
-    }
 };
 
-// Thin links (FP32): per site 4 links = 2 groups of 2 links, tiled like the
-// Dslash links: unit e of group gi of site s at u4v index ((s/64)*2 + gi)*9*64 + e*64 + s%64.
-__device__ __forceinline__ void load_thin(const void *base, int s, int mu, cx<float> w[9]) {
-    const u4v *b = (const u4v *)base + ((size_t)((s >> 6) * 2 + (mu >> 1)) * 9) * 64 + (s & 63);
-    const int sl = mu & 1;
-    // complex entries 9 sl .. 9 sl + 8 of the 18 in the group record
+struct SiteGeo {
+    int s;     // lex index
+    int c[4];  // coordinates
+    int par;   // (x + y + z + t) & 1
+};
+
+__device__ __forceinline__ SiteGeo site_geo(const Lex &g, int s) {
+    SiteGeo o;
+    o.s = s;
+    int r = s;
+    o.c[0] = r % g.L[0];
+    r /= g.L[0];
+    o.c[1] = r % g.L[1];
+    r /= g.L[1];
+    o.c[2] = r % g.L[2];
+    o.c[3] = r / g.L[2];
+    o.par = (o.c[0] + o.c[1] + o.c[2] + o.c[3]) & 1;
+    return o;
+}
+
+// lex index of x + d mu, d = +1 or -1
+template <int MU>
+__device__ __forceinline__ int hop(const Lex &g, const SiteGeo &x, int d) {
+    int stride = 1;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-        const int idx = 9 * sl + c;  // complex index in the 144-byte record
-        const u4v raw = b[(idx >> 1) * 64];
-        const f4v u = __builtin_bit_cast(f4v, raw);
-        w[c] = (idx & 1) ? cx<float>{u.z, u.w} : cx<float>{u.x, u.y};
+    for (int k = 0; k < MU; ++k) stride *= g.L[k];
+    const int c = x.c[MU], Lm = g.L[MU];
+    if (d > 0) return c == Lm - 1 ? x.s - (Lm - 1) * stride : x.s + stride;
+    return c == 0 ? x.s + (Lm - 1) * stride : x.s - stride;
+}
+
+// Enumerated site -> lex index: all sites in lex order, or the even sites in
+// checkerboard order (h = lex / 2).
+template <int MODE>
+__device__ __forceinline__ int site_of(const Lex &g, int idx) {
+    if constexpr (MODE == IO_FULL) {
+        return idx;
+    } else {
+        const int lxh = g.L[0] >> 1;
+        const int xh = idx % lxh, r = idx / lxh;
+        const int y = r % g.L[1], z = (r / g.L[1]) % g.L[2], t = r / (g.L[1] * g.L[2]);
+        return 2 * xh + ((y + z + t) & 1) + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
     }
 }
 
-__global__ __launch_bounds__(256) void k_pack_thin(Lex g, const double *__restrict__ U, void *dst) {
+// Workgroups are handed to the eight XCDs round-robin (block b to XCD b % 8),
+// and each XCD has its own L2.  Renumber blocks so that every XCD works on one
+// contiguous range of sites: the lattice neighbours of a block's sites then
+// sit in the same L2 (all but the outermost direction).  A bijection on
+// [0, nblk) for any nblk.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+    const int q = nblk >> 3, rem = nblk & 7, r = b & 7, k = b >> 3;
+    return r < rem ? r * (q + 1) + k : rem * (q + 1) + (r - rem) * q + k;
+}
+
+// ------------------------------------------------------------------ thin links (FP16)
+template <int MU>
+__device__ __forceinline__ void load_link(const void *thin, int s, cx<float> w[9]) {
+    const u4v *b = (const u4v *)thin + (size_t)(s >> 6) * 9 * 64 + (s & 63);
+    constexpr int U0 = (9 * MU) / 4, OFF = (9 * MU) % 4;  // first unit, first word in it
+    const u4v r0 = b[U0 * 64], r1 = b[(U0 + 1) * 64], r2 = b[(U0 + 2) * 64];
+    const unsigned wd[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const unsigned v = wd[OFF + k];
+        const h2v h = __builtin_bit_cast(h2v, v);
+        w[k] = {(float)h.x, (float)h.y};
+    }
+}
+
+// Pack canonical FP64 thin links [V][4][3][3] complex into the FP16 records;
+// *bad is set if an entry is not finite or too large for FP16.
+__global__ __launch_bounds__(256) void k_pack_thin(Lex g, const double *__restrict__ U, void *dst, unsigned *bad) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int mu = blockIdx.y;
     if (s >= g.V) return;
-    char *rec = (char *)dst + ((size_t)((s >> 6) * 2 + (mu >> 1)) * 9) * 1024 + (size_t)(s & 63) * 16;
+    unsigned *words = (unsigned *)dst;
     const double *src = U + ((size_t)s * 4 + mu) * 18;
-    for (int c = 0; c < 9; ++c) {
-        const int off = ((mu & 1) * 9 + c) * 8;
-        *(f2v *)(rec + (size_t)(off >> 4) * 1024 + (off & 15)) = f2v{(float)src[2 * c], (float)src[2 * c + 1]};
+    bool ok = true;
+    for (int k = 0; k < 9; ++k) {
+        const int wi = 9 * mu + k, e = wi >> 2, q = wi & 3;
+        const double re = src[2 * k], im = src[2 * k + 1];
+        ok = ok && fabs(re) < 32768.0 && fabs(im) < 32768.0;  // false for NaN as well
+        const h2v h = {(_Float16)(float)re, (_Float16)(float)im};
+        words[((size_t)(s >> 6) * 9 + e) * 256 + (size_t)(s & 63) * 4 + q] = __builtin_bit_cast(unsigned, h);
     }
+    if (!ok) atomicOr(bad, 1u);
 }
 
 // ------------------------------------------------------------------ activations
-// Input / output modes of a layer:
-//   IO_FULL: C channels on all V sites, channel b = FP32 spinor buffer b of a
-//            stack with vh = V (lexicographic site order);
-//   IO_EVEN: one channel on even sites only, an FP32 spinor of the public
-//            layout (checkerboard order); odd sites read as zero.
-enum { IO_FULL = 0, IO_EVEN = 1 };
+__device__ __forceinline__ float bf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
-template <int MODE>
-__device__ __forceinline__ void load_act(const Lex &g, const float *buf, int b, int s, cx<float> v[3]) {
-    if constexpr (MODE == IO_FULL) {
-        Spinor<F32>{const_cast<float *>(buf), g.V}.rhs(b).load(s, v);
-    } else {
-        if (g.parity(s) == 0) {
-            Spinor<F32>{const_cast<float *>(buf), g.V / 2}.load(s >> 1, v);
-        } else {
+// Channels 4 h .. 4 h + 3 of the six units of site s: v[u] = 8 bytes of unit u.
+__device__ __forceinline__ void load_act_half(const void *buf, int s, int h, u2v v[6]) {
+    const u2v *b = (const u2v *)buf + ((size_t)(s >> 6) * 6 * 64 + (s & 63)) * 2 + h;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v[c] = {0.f, 0.f};
+    for (int u = 0; u < 6; ++u) v[u] = b[(size_t)u * 128];
+}
+
+// channel q (0..3) of an 8-byte half unit
+__device__ __forceinline__ float half_chan(const u2v &v, int q) {
+    const unsigned w = (q < 2) ? v.x : v.y;
+    return (q & 1) ? bf_hi(w) : bf_lo(w);
+}
+
+// ------------------------------------------------------------------ transport into LDS
+// Path P (0 identity, 1..4 forward hop mu = P - 1, 5..8 backward hop
+// mu = P - 5, 9 = padding) of channels 4h .. 4h + 3 of a hidden input at
+// site x; writes the 3 colours x {re, im} x 4 channels to the LDS columns of
+// the site at K offset koff (+ 8 ri + 4 h).
+template <int P>
+__device__ __forceinline__ void transport_hidden(const Lex &g, const void *thin, const void *in, const SiteGeo &x,
+                                                 bool valid, int h, __bf16 *col, int koff) {
+    float tr[3][4], ti[3][4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tr[a][q] = ti[a][q] = 0.f;
+    if (P < 9 && valid) {
+        int nb = x.s;
+        cx<float> w[9];
+        if constexpr (P >= 1 && P <= 4) {
+            nb = hop<P - 1>(g, x, +1);
+            load_link<P - 1>(thin, x.s, w);
+        } else if constexpr (P >= 5 && P <= 8) {
+            nb = hop<P - 5>(g, x, -1);
+            load_link<P - 5>(thin, nb, w);
         }
+        u2v v[6];
+        load_act_half(in, nb, h, v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cx<float> vb[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vb[c] = {half_chan(v[2 * c], q), half_chan(v[2 * c + 1], q)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cx<float> t = {0.f, 0.f};
+                if constexpr (P == 0) {
+                    t = vb[a];
+                } else if constexpr (P <= 4) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) cmac(t, w[3 * a + c], vb[c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {  // conj(U[c][a]) v[c]
+                        const cx<float> u = w[3 * c + a];
+                        t.re += u.re * vb[c].re + u.im * vb[c].im;
+                        t.im += u.re * vb[c].im - u.im * vb[c].re;
+                    }
+                }
+                tr[a][q] = t.re;
+                ti[a][q] = t.im;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const b4v r = {(__bf16)tr[a][0], (__bf16)tr[a][1], (__bf16)tr[a][2], (__bf16)tr[a][3]};
+        const b4v i = {(__bf16)ti[a][0], (__bf16)ti[a][1], (__bf16)ti[a][2], (__bf16)ti[a][3]};
+        *(b4v *)(col + a * BT_LD + koff + 4 * h) = r;
+        *(b4v *)(col + a * BT_LD + koff + 8 + 4 * h) = i;
     }
 }
 
-// Transported inputs of 16 sites into LDS: Bt[col][k], col = site*3 + colour,
-// k = p*CIN + b (real part) and K + p*CIN + b (imaginary part).
-template <int CIN, int INM>
-__device__ __forceinline__ void transport_tile(const Lex &g, const void *thin, const float *in, int site, bool valid,
-                                               int j, __bf16 (*Bt)[kpad(CIN) + 8]) {
-    constexpr int K = 9 * CIN;
-    const int s = threadIdx.x & 15;
-    for (int p = j; p < 9; p += 4) {
-        cx<float> w[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) w[c] = {0.f, 0.f};  // tail sites multiply zeros, never garbage
-        int nb = site;
-        bool adj = false;
-        if (valid && p != 0) {
-            const int mu = (p - 1) & 3;
-            if (p <= 4) {
-                nb = g.hop(site, mu, +1);
-                load_thin(thin, site, mu, w);
+// Path P of the one-channel even-site input (FP32 public spinor) at site x;
+// lane half h writes the re (h = 0) or im (h = 1) parts at K = 2P + h.
+template <int P>
+__device__ __forceinline__ void transport_even_path(const Lex &g, const void *thin, const float *in, const SiteGeo &x,
+                                                    bool valid, int h, __bf16 *col) {
+    cx<float> t[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+    // the input lives on even sites: path 0 needs x even, the hops x odd
+    const bool live = valid && (P == 0 ? x.par == 0 : x.par == 1);
+    if (live) {
+        const int vh = g.V / 2;
+        if constexpr (P == 0) {
+            Spinor<F32>{const_cast<float *>(in), vh}.load(x.s >> 1, t);
+        } else {
+            cx<float> w[9], v[3];
+            int nb;
+            if constexpr (P <= 4) {
+                nb = hop<P - 1>(g, x, +1);
+                load_link<P - 1>(thin, x.s, w);
             } else {
-                nb = g.hop(site, mu, -1);
-                load_thin(thin, nb, mu, w);
-                adj = true;
+                nb = hop<P - 5>(g, x, -1);
+                load_link<P - 5>(thin, nb, w);
             }
-        }
-        for (int b = 0; b < CIN; ++b) {
-            cx<float> v[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}}, t[3];
-            if (valid) load_act<INM>(g, in, b, nb, v);
-            if (p == 0) {
+            Spinor<F32>{const_cast<float *>(in), vh}.load(nb >> 1, v);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) t[c] = v[c];
-            } else {
+            for (int a = 0; a < 3; ++a) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    t[a] = {0.f, 0.f};
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (adj) {  // conj(U[c][a]) v[c]
-                            const cx<float> u = w[3 * c + a];
-                            t[a].re += u.re * v[c].re + u.im * v[c].im;
-                            t[a].im += u.re * v[c].im - u.im * v[c].re;
-                        } else {
-                            cmac(t[a], w[3 * a + c], v[c]);
-                        }
+                for (int c = 0; c < 3; ++c) {
+                    if constexpr (P <= 4) {
+                        cmac(t[a], w[3 * a + c], v[c]);
+                    } else {
+                        const cx<float> u = w[3 * c + a];
+                        t[a].re += u.re * v[c].re + u.im * v[c].im;
+                        t[a].im += u.re * v[c].im - u.im * v[c].re;
                     }
                 }
             }
-            const int k = p * CIN + b;
+        }
+    }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Bt[s * 3 + c][k] = (__bf16)t[c].re;
-                Bt[s * 3 + c][K + k] = (__bf16)t[c].im;
-            }
+    for (int a = 0; a < 3; ++a) col[a * BT_LD + 2 * P + h] = (__bf16)(h ? t[a].im : t[a].re);
+}
+
+// All nine paths of the even-site input, zeros in the padding K = 18..31.
+__device__ __forceinline__ void transport_even(const Lex &g, const void *thin, const float *in, const SiteGeo &x,
+                                               bool valid, int h, __bf16 *col) {
+    transport_even_path<0>(g, thin, in, x, valid, h, col);
+    transport_even_path<1>(g, thin, in, x, valid, h, col);
+    transport_even_path<2>(g, thin, in, x, valid, h, col);
+    transport_even_path<3>(g, thin, in, x, valid, h, col);
+    transport_even_path<4>(g, thin, in, x, valid, h, col);
+    transport_even_path<5>(g, thin, in, x, valid, h, col);
+    transport_even_path<6>(g, thin, in, x, valid, h, col);
+    transport_even_path<7>(g, thin, in, x, valid, h, col);
+    transport_even_path<8>(g, thin, in, x, valid, h, col);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) col[a * BT_LD + 18 + 2 * j + h] = (__bf16)0.f;
+}
+
+// Transported input chunk q (K rows 32 q .. 32 q + 31) of the lane pair's site.
+template <int INM>
+__device__ __forceinline__ void transport_chunk(int q, const Lex &g, const void *thin, const void *in,
+                                                const SiteGeo &x, bool valid, int h, __bf16 *col) {
+    if constexpr (INM == IO_EVEN) {
+        transport_even(g, thin, (const float *)in, x, valid, h, col);
+    } else {
+        switch (q) {
+            case 0:
+                transport_hidden<0>(g, thin, in, x, valid, h, col, 0);
+                transport_hidden<1>(g, thin, in, x, valid, h, col, 16);
+                break;
+            case 1:
+                transport_hidden<2>(g, thin, in, x, valid, h, col, 0);
+                transport_hidden<3>(g, thin, in, x, valid, h, col, 16);
+                break;
+            case 2:
+                transport_hidden<4>(g, thin, in, x, valid, h, col, 0);
+                transport_hidden<5>(g, thin, in, x, valid, h, col, 16);
+                break;
+            case 3:
+                transport_hidden<6>(g, thin, in, x, valid, h, col, 0);
+                transport_hidden<7>(g, thin, in, x, valid, h, col, 16);
+                break;
+            default:
+                transport_hidden<8>(g, thin, in, x, valid, h, col, 0);
+                transport_hidden<9>(g, thin, in, x, valid, h, col, 16);
+                break;
         }
     }
 }
 
 // ------------------------------------------------------------------ layer kernel
-// amat: bf16 [16][kpad(CIN)] real-block weight matrix (rows 0..7 Re, 8..15 Im of
-// the output channels).  Sites: OUTM == IO_FULL -> all V sites in lex order;
-// IO_EVEN -> even sites in checkerboard order (output to a public FP32 spinor).
-template <int CIN, int COUT, int INM, int OUTM>
-__global__ __launch_bounds__(64 * NN_WAVES) void k_nn_layer(Lex g, const void *thin, const float *__restrict__ in,
-                                                            float *__restrict__ out, const __bf16 *__restrict__ amat) {
-    constexpr int KP = kpad(CIN);
-    __shared__ __attribute__((aligned(16))) __bf16 Bt[NN_WAVES][NN_COLS][KP + 8];
-    __shared__ float Ct[NN_WAVES][16][NN_COLS + 4];
+// amat: bf16 [16][kp_of(INM)], rows 0..7 Re and 8..15 Im of the output
+// channels.  OUTM == IO_FULL: all V sites, output BF16 hidden units;
+// IO_EVEN: even sites in checkerboard order, output channel 0 as an FP32
+// public spinor.
+template <int INM, int OUTM>
+__global__ __launch_bounds__(64 * NN_WAVES) void k_nn_layer(Lex g, const void *thin, const void *__restrict__ in,
+                                                            void *__restrict__ out, const __bf16 *__restrict__ amat) {
+    constexpr int KP = kp_of(INM);
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[NN_WAVES][NW_COLS][BT_LD];
+    __shared__ float Of[NN_WAVES][NW_SITES][6];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, j = l >> 4;
     const int nsites = OUTM == IO_FULL ? g.V : g.V / 2;
-    const int idx = (blockIdx.x * NN_WAVES + w) * NN_SITES + i;
+    const int base = (xcd_block(blockIdx.x, gridDim.x) * NN_WAVES + w) * NW_SITES;
+    const int sl = l >> 1, h = l & 1;  // lane pair (site, half)
+    const int idx = base + sl;
     const bool valid = idx < nsites;
-    int site = idx;
-    if (OUTM == IO_EVEN && valid) {  // checkerboard index of an even site -> lex
-        const int lxh = g.L[0] >> 1;
-        const int xh = idx % lxh, r = idx / lxh;
-        const int y = r % g.L[1], z = (r / g.L[1]) % g.L[2], t = r / (g.L[1] * g.L[2]);
-        site = 2 * xh + ((y + z + t) & 1) + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
-    }
-    // zero the K padding rows of this wave's tile
-    for (int e = l; e < NN_COLS * (KP - 18 * CIN); e += 64) {
-        const int col = e % NN_COLS, k = 18 * CIN + e / NN_COLS;
-        Bt[w][col][k] = (__bf16)0.f;
-    }
-    transport_tile<CIN, INM>(g, thin, in, site, valid, j, Bt[w]);
-    __syncthreads();
+    const SiteGeo x = site_geo(g, valid ? site_of<OUTM>(g, idx) : 0);
+    __bf16 *col = &Bt[w][sl * 3][0];
 
-    f4v acc[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    f4v acc[6];
 #pragma unroll
-    for (int ks = 0; ks < KP / 32; ++ks) {
-        const b8v a = *(const b8v *)(amat + i * KP + ks * 32 + j * 8);
+    for (int cb = 0; cb < 6; ++cb) acc[cb] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int cb = 0; cb < 3; ++cb) {
-            const b8v b = *(const b8v *)(&Bt[w][cb * 16 + i][ks * 32 + j * 8]);
+    for (int q = 0; q < KP / 32; ++q) {
+        transport_chunk<INM>(q, g, thin, in, x, valid, h, col);
+        __syncthreads();
+        const b8v a = *(const b8v *)(amat + i * KP + q * 32 + j * 8);
+#pragma unroll
+        for (int cb = 0; cb < 6; ++cb) {
+            const b8v b = *(const b8v *)(&Bt[w][cb * 16 + i][j * 8]);
             acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
         }
+        __syncthreads();
     }
-#pragma unroll
-    for (int cb = 0; cb < 3; ++cb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Ct[w][j * 4 + q][cb * 16 + i] = acc[cb][q];
-    __syncthreads();
 
-    // write: lane handles (channel a, site s) pairs
-    for (int e = l; e < COUT * NN_SITES; e += 64) {
-        const int a = e / NN_SITES, s = e % NN_SITES;
-        const int oidx = (blockIdx.x * NN_WAVES + w) * NN_SITES + s;
-        if (oidx >= nsites) continue;
-        cx<float> v[3];
+    // lane (i, j) holds rows 4j .. 4j + 3 of column cb * 16 + i
+    if constexpr (OUTM == IO_FULL) {
+        __bf16 *Ot = &Bt[w][0][0];  // staging [32 sites][48] (unit u = 2 colour + ri, channel)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = {Ct[w][a][s * 3 + c], Ct[w][8 + a][s * 3 + c]};
-        if constexpr (OUTM == IO_FULL) Spinor<F32>{out, g.V}.rhs(a).store(oidx, v);
-        else Spinor<F32>{out, g.V / 2}.store(oidx, v);
+        for (int cb = 0; cb < 6; ++cb) {
+            const int cl = cb * 16 + i, s = cl / 3, c = cl % 3;
+            const b4v v = {(__bf16)acc[cb][0], (__bf16)acc[cb][1], (__bf16)acc[cb][2], (__bf16)acc[cb][3]};
+            *(b4v *)(Ot + s * 48 + (2 * c + (j >> 1)) * 8 + (j & 1) * 4) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int e = t * 64 + l, s = e & 31, u = e >> 5;
+            const int S = base + s;
+            if (S < nsites) {
+                const u4v val = *(const u4v *)(Ot + s * 48 + u * 8);
+                ((u4v *)out)[((size_t)(S >> 6) * 6 + u) * 64 + (S & 63)] = val;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < 6; ++cb) {
+            const int cl = cb * 16 + i, s = cl / 3, c = cl % 3;
+            if (j == 0) Of[w][s][2 * c] = acc[cb][0];      // row 0: Re of channel 0
+            if (j == 2) Of[w][s][2 * c + 1] = acc[cb][0];  // row 8: Im of channel 0
+        }
+        __syncthreads();
+        if (l < NW_SITES && base + l < nsites) {
+            cx<float> v[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = {Of[w][l][2 * c], Of[w][l][2 * c + 1]};
+            Spinor<F32>{(float *)out, g.V / 2}.store(base + l, v);
+        }
     }
 }
 
 // ------------------------------------------------------------------ weight gradient
-// partial[blk][16][KC] (KC = 16 * ceil(9 CIN / 16)): C[r][k] = sum over this
-// block's (site, colour) of  r < 8: Re(g_r conj t_k),  r >= 8: Im(g_{r-8} conj t_k).
-// The upstream gradient uses mode GM (IO_FULL: COUT channels on all sites, or
-// IO_EVEN: one channel on even sites); sites are enumerated like k_nn_layer with OUTM = GM.
-template <int CIN, int COUT, int INM, int GM>
-__global__ __launch_bounds__(64 * NN_WAVES) void k_nn_wgrad(Lex g, const void *thin, const float *__restrict__ in,
-                                                            const float *__restrict__ grad, float *__restrict__ partial) {
-    constexpr int K = 9 * CIN;
-    constexpr int KP = kpad(CIN);
-    constexpr int NCB = (K + 15) / 16;
-    __shared__ __attribute__((aligned(16))) __bf16 Bt[NN_WAVES][NN_COLS][KP + 8];
-    __shared__ __attribute__((aligned(16))) __bf16 Gt[NN_WAVES][16][2 * NN_COLS + 8];  // A2 rows, m = 0..95
-    __shared__ float Red[NN_WAVES][16][16 * NCB];
+// Per block: partial[blk][16][KC], KC = 80 (hidden input: column 8 p + b) or
+// 16 (even input: column p), C[r][n] = sum over the block's (site, colour) of
+// r < 8: Re(g_r conj t_n), r >= 8: Im(g_{r-8} conj t_n).  The upstream gradient
+// g has mode GM (IO_FULL: BF16 hidden units on all sites; IO_EVEN: channel 0
+// as an FP32 public spinor on even sites); sites are enumerated like the
+// layer kernel with OUTM = GM.
+template <int INM, int GM>
+__global__ __launch_bounds__(64 * NN_WAVES) void k_nn_wgrad(Lex g, const void *thin, const void *__restrict__ in,
+                                                            const void *__restrict__ grad, float *__restrict__ partial) {
+    constexpr int KP = kp_of(INM);
+    constexpr int NQ = KP / 32;  // chunks
+    constexpr int KC = INM == IO_EVEN ? 16 : 80;
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[NN_WAVES][NW_COLS][BT_LD];
+    __shared__ __attribute__((aligned(16))) __bf16 Gt[NN_WAVES][16][GT_LD];
+    __shared__ float Red[NN_WAVES][16][KC];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, j = l >> 4;
     const int nsites = GM == IO_FULL ? g.V : g.V / 2;
-    const int idx = (blockIdx.x * NN_WAVES + w) * NN_SITES + i;
+    const int base = (xcd_block(blockIdx.x, gridDim.x) * NN_WAVES + w) * NW_SITES;
+    const int sl = l >> 1, h = l & 1;
+    const int idx = base + sl;
     const bool valid = idx < nsites;
-    int site = idx;
-    if (GM == IO_EVEN && valid) {
-        const int lxh = g.L[0] >> 1;
-        const int xh = idx % lxh, r = idx / lxh;
-        const int y = r % g.L[1], z = (r / g.L[1]) % g.L[2], t = r / (g.L[1] * g.L[2]);
-        site = 2 * xh + ((y + z + t) & 1) + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
-    }
-    transport_tile<CIN, INM>(g, thin, in, site, valid, j, Bt[w]);
-    // A2 = [[Gr, Gi], [Gi, -Gr]] over m = (site, colour) (Re block then Im block)
-    for (int e = l; e < 8 * NN_SITES; e += 64) {
-        const int a = e / NN_SITES, s = e % NN_SITES;
-        const int gidx = (blockIdx.x * NN_WAVES + w) * NN_SITES + s;
-        cx<float> v[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-        if (a < COUT && gidx < nsites) {
-            if constexpr (GM == IO_FULL) Spinor<F32>{const_cast<float *>(grad), g.V}.rhs(a).load(gidx, v);
-            else Spinor<F32>{const_cast<float *>(grad), g.V / 2}.load(gidx, v);
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int m = s * 3 + c;
-            Gt[w][a][m] = (__bf16)v[c].re;
-            Gt[w][a][NN_COLS + m] = (__bf16)v[c].im;
-            Gt[w][8 + a][m] = (__bf16)v[c].im;
-            Gt[w][8 + a][NN_COLS + m] = (__bf16)(-v[c].re);
-        }
-    }
-    __syncthreads();
+    const SiteGeo x = site_geo(g, valid ? site_of<GM>(g, idx) : 0);
+    __bf16 *col = &Bt[w][sl * 3][0];
 
-    f4v acc[NCB];
+    // A2 = [[Gr, Gi], [Gi, -Gr]] over m = (site, colour): re block m < 96, im block m >= 96
+    for (int e = l; e < 16 * GT_LD; e += 64) (&Gt[w][0][0])[e] = (__bf16)0.f;
+    __syncthreads();
+    if constexpr (GM == IO_FULL) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f4v{0, 0, 0, 0};
+        for (int t = 0; t < 3; ++t) {
+            const int e = t * 64 + l, s = e & 31, u = e >> 5, c = u >> 1, ri = u & 1;
+            const int S = base + s, m = s * 3 + c;
+            u4v val = {0u, 0u, 0u, 0u};
+            if (S < nsites) val = ((const u4v *)grad)[((size_t)(S >> 6) * 6 + u) * 64 + (S & 63)];
+            const unsigned wd[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
-    for (int ks = 0; ks < (2 * NN_COLS) / 32; ++ks) {
-        const b8v a = *(const b8v *)(&Gt[w][i][ks * 32 + j * 8]);
+            for (int a = 0; a < 8; ++a) {
+                const float v = (a & 1) ? bf_hi(wd[a >> 1]) : bf_lo(wd[a >> 1]);
+                if (ri == 0) {
+                    Gt[w][a][m] = (__bf16)v;
+                    Gt[w][8 + a][NW_COLS + m] = (__bf16)(-v);
+                } else {
+                    Gt[w][a][NW_COLS + m] = (__bf16)v;
+                    Gt[w][8 + a][m] = (__bf16)v;
+                }
+            }
+        }
+    } else {
+        if (l < NW_SITES) {
+            cx<float> v[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+            if (base + l < nsites) Spinor<F32>{(float *)grad, g.V / 2}.load(base + l, v);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-            const int k = cb * 16 + i;
+            for (int c = 0; c < 3; ++c) {
+                const int m = l * 3 + c;
+                Gt[w][0][m] = (__bf16)v[c].re;
+                Gt[w][8][NW_COLS + m] = (__bf16)(-v[c].re);
+                Gt[w][0][NW_COLS + m] = (__bf16)v[c].im;
+                Gt[w][8][m] = (__bf16)v[c].im;
+            }
+        }
+    }
+
+    f4v acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        transport_chunk<INM>(q, g, thin, in, x, valid, h, col);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < (2 * NW_COLS) / 32; ++ks) {
+            const b8v a = *(const b8v *)(&Gt[w][i][ks * 32 + j * 8]);
+            const int ri = ks >= 3 ? 1 : 0;
             b8v b;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int m = ks * 32 + j * 8 + q;
-                __bf16 v = (__bf16)0.f;
-                if (k < K) v = m < NN_COLS ? Bt[w][m][k] : Bt[w][m - NN_COLS][K + k];
-                b[q] = v;
+            for (int e = 0; e < 8; ++e) {
+                const int m = (ks % 3) * 32 + j * 8 + e;  // column of the transported tile
+                __bf16 v;
+                if constexpr (INM == IO_EVEN) v = i < 9 ? Bt[w][m][2 * i + ri] : (__bf16)0.f;
+                else v = Bt[w][m][(i >> 3) * 16 + ri * 8 + (i & 7)];
+                b[e] = v;
             }
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
         }
+        __syncthreads();
     }
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+    for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Red[w][j * 4 + q][cb * 16 + i] = acc[cb][q];
+        for (int r = 0; r < 4; ++r) Red[w][j * 4 + r][q * 16 + i] = acc[q][r];
     __syncthreads();
     // sum the block's waves in a fixed order, write the block partial
-    for (int e = threadIdx.x; e < 16 * 16 * NCB; e += blockDim.x) {
-        const int r = e / (16 * NCB), k = e % (16 * NCB);
+    for (int e = threadIdx.x; e < 16 * KC; e += blockDim.x) {
+        const int r = e / KC, k = e % KC;
         float s = 0.f;
         for (int ww = 0; ww < NN_WAVES; ++ww) s += Red[ww][r][k];
-        partial[(size_t)blockIdx.x * 16 * 16 * NCB + e] = s;
+        partial[(size_t)blockIdx.x * 16 * KC + e] = s;
     }
 }
 
-// grad[p][a][b] (complex double) += sum over blocks (fixed order) of the partials
-__global__ void k_nn_wgrad_reduce(const float *__restrict__ partial, int nblk, int cin, int cout, double *grad) {
-    const int K = 9 * cin, KC = 16 * ((K + 15) / 16);
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (a, k)
-    if (e >= cout * K) return;
-    const int a = e / K, k = e % K;
+// Two-stage fixed-order sum of the block partials.  Stage 1: segment sg of
+// the blocks, every entry e of the 16 x KC partial: fold[sg][e].
+constexpr int NN_FOLD = 64;  // segments
+
+__global__ __launch_bounds__(256) void k_nn_wgrad_fold(const float *__restrict__ partial, int nblk, int nent,
+                                                      float *__restrict__ fold) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x, sg = blockIdx.y;
+    if (e >= nent) return;
+    const int per = (nblk + NN_FOLD - 1) / NN_FOLD;
+    const int b0 = sg * per, b1 = min(nblk, b0 + per);
+    float s = 0.f;
+    for (int b = b0; b < b1; ++b) s += partial[(size_t)b * nent + e];
+    fold[(size_t)sg * nent + e] = s;
+}
+
+// Stage 2: grad[p][a][b] (complex double) += sum over the segments (fixed order).
+__global__ void k_nn_wgrad_reduce(const float *__restrict__ fold, int inm, int cin, int cout, double *grad) {
+    const int KC = inm == IO_EVEN ? 16 : 80;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (a, p, b)
+    if (e >= cout * 9 * cin) return;
+    const int a = e / (9 * cin), pb = e % (9 * cin), p = pb / cin, b = pb % cin;
+    const int n = inm == IO_EVEN ? p : 8 * p + b;
     double re = 0.0, im = 0.0;
-    for (int blk = 0; blk < nblk; ++blk) {
-        const float *P = partial + (size_t)blk * 16 * KC;
-        re += P[a * KC + k];
-        im += P[(8 + a) * KC + k];
+    for (int sg = 0; sg < NN_FOLD; ++sg) {
+        const float *P = fold + (size_t)sg * 16 * KC;
+        re += P[a * KC + n];
+        im += P[(8 + a) * KC + n];
     }
-    const int p = k / cin, b = k % cin;
     double *gp = grad + 2 * (((size_t)p * cout + a) * cin + b);
     gp[0] += re;
     gp[1] += im;
 }
 
-// real-block bf16 matrix of a layer (transposed = the adjoint layer)
-__global__ void k_nn_build_amat(const double *__restrict__ W, int cin, int cout, int transposed, __bf16 *amat) {
+// Real-block bf16 matrix of a layer (transposed = the adjoint layer), in the
+// K order of the input mode: hidden k = 16 p + 8 ri + b, even k = 2 p + ri.
+__global__ void k_nn_build_amat(const double *__restrict__ W, int cin, int cout, int transposed, int inm,
+                                __bf16 *amat) {
     // forward: out channels cout, in channels cin; transposed: out = cin, in = cout
     const int ci = transposed ? cout : cin, co = transposed ? cin : cout;
-    const int K = 9 * ci, KP = ((2 * K + 31) / 32) * 32;
+    const int KP = kp_of(inm);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 16 * KP) return;
     const int r = e / KP, k = e % KP;
+    int p, ri, b;
+    if (inm == IO_EVEN) {
+        p = k >> 1;
+        ri = k & 1;
+        b = 0;
+    } else {
+        p = k >> 4;
+        ri = (k >> 3) & 1;
+        b = k & 7;
+    }
     double val = 0.0;
     const int a = r & 7;
-    if (a < co && k < 2 * K) {
-        const int kk = k % K;
-        const int p = kk / ci, b = kk % ci;  // y_a += W'_p[a][b] t_{p,b}
+    if (p < 9 && a < co && b < ci) {
         double wr, wi;
-        if (!transposed) {
+        if (!transposed) {  // y_a += W_p[a][b] t_{p,b}
             const double *src = W + 2 * (((size_t)p * cout + a) * cin + b);
             wr = src[0];
             wi = src[1];
@@ -348,7 +561,7 @@ __global__ void k_nn_build_amat(const double *__restrict__ W, int cin, int cout,
             wr = src[0];
             wi = -src[1];
         }
-        const bool im_row = r >= 8, im_col = k >= K;
+        const bool im_row = r >= 8, im_col = ri == 1;
         // [[Wr, -Wi], [Wi, Wr]]
         val = !im_row ? (!im_col ? wr : -wi) : (!im_col ? wi : wr);
     }
@@ -430,106 +643,80 @@ __global__ void k_nn_adam(double *w, double *m, double *v, const double *g, int 
 }
 
 // ------------------------------------------------------------------ dispatch
-template <int CIN, int COUT>
-static void layer_launch(const Lex &L, const void *thin, int inm, int outm, const float *in, float *out,
-                         const __bf16 *amat, hipStream_t s) {
-    const int nsites = outm == IO_FULL ? L.V : L.V / 2;
-    const dim3 grid((nsites + NN_SITES * NN_WAVES - 1) / (NN_SITES * NN_WAVES)), block(64 * NN_WAVES);
+static Lex lex_of(const NnGeom &G) { return Lex{{G.L[0], G.L[1], G.L[2], G.L[3]}, G.V}; }
+
+static int grid_blocks(int nsites) { return (nsites + NB_SITES - 1) / NB_SITES; }
+
+bool nn_channels_supported(int c) { return c >= 1 && c <= 8; }
+
+size_t nn_act_bytes(const NnGeom &G) { return (size_t)((G.V + 63) / 64) * 6 * 1024; }
+
+size_t nn_amat_elems(int inm) { return (size_t)16 * kp_of(inm); }
+
+size_t nn_wgrad_partial_floats(const NnGeom &G) { return ((size_t)grid_blocks(G.V) + NN_FOLD) * 16 * 80; }
+
+size_t nn_thin_bytes(const NnGeom &G) { return (size_t)((G.V + 63) / 64) * 9 * 1024 + 256; }
+
+int nn_layer(const NnGeom &G, const void *thin, int inm, int outm, const void *in, void *out, const void *amat,
+             hipStream_t s) {
+    const Lex L = lex_of(G);
+    const dim3 grid(grid_blocks(outm == IO_FULL ? G.V : G.V / 2)), block(64 * NN_WAVES);
+    const __bf16 *A = (const __bf16 *)amat;
     if (inm == IO_FULL && outm == IO_FULL)
-        hipLaunchKernelGGL((k_nn_layer<CIN, COUT, IO_FULL, IO_FULL>), grid, block, 0, s, L, thin, in, out, amat);
+        hipLaunchKernelGGL((k_nn_layer<IO_FULL, IO_FULL>), grid, block, 0, s, L, thin, in, out, A);
     else if (inm == IO_EVEN && outm == IO_FULL)
-        hipLaunchKernelGGL((k_nn_layer<CIN, COUT, IO_EVEN, IO_FULL>), grid, block, 0, s, L, thin, in, out, amat);
+        hipLaunchKernelGGL((k_nn_layer<IO_EVEN, IO_FULL>), grid, block, 0, s, L, thin, in, out, A);
     else if (inm == IO_FULL && outm == IO_EVEN)
-        hipLaunchKernelGGL((k_nn_layer<CIN, COUT, IO_FULL, IO_EVEN>), grid, block, 0, s, L, thin, in, out, amat);
+        hipLaunchKernelGGL((k_nn_layer<IO_FULL, IO_EVEN>), grid, block, 0, s, L, thin, in, out, A);
     else
-        hipLaunchKernelGGL((k_nn_layer<CIN, COUT, IO_EVEN, IO_EVEN>), grid, block, 0, s, L, thin, in, out, amat);
+        hipLaunchKernelGGL((k_nn_layer<IO_EVEN, IO_EVEN>), grid, block, 0, s, L, thin, in, out, A);
+    HISQ_HIP_CHECK(hipGetLastError());
+    return HISQ_OK;
 }
 
-template <int CIN, int COUT>
-static int wgrad_launch(const Lex &L, const void *thin, int inm, int gm, const float *in, const float *grad,
-                        float *partial, hipStream_t s) {
-    const int nsites = gm == IO_FULL ? L.V : L.V / 2;
-    const int nblk = (nsites + NN_SITES * NN_WAVES - 1) / (NN_SITES * NN_WAVES);
+int nn_wgrad(const NnGeom &G, const void *thin, int cin, int cout, int inm, int gm, const void *in, const void *grad,
+             float *partial, double *gacc, hipStream_t s) {
+    const Lex L = lex_of(G);
+    const int nblk = grid_blocks(gm == IO_FULL ? G.V : G.V / 2);
     const dim3 grid(nblk), block(64 * NN_WAVES);
     if (inm == IO_FULL && gm == IO_FULL)
-        hipLaunchKernelGGL((k_nn_wgrad<CIN, COUT, IO_FULL, IO_FULL>), grid, block, 0, s, L, thin, in, grad, partial);
+        hipLaunchKernelGGL((k_nn_wgrad<IO_FULL, IO_FULL>), grid, block, 0, s, L, thin, in, grad, partial);
     else if (inm == IO_EVEN && gm == IO_FULL)
-        hipLaunchKernelGGL((k_nn_wgrad<CIN, COUT, IO_EVEN, IO_FULL>), grid, block, 0, s, L, thin, in, grad, partial);
+        hipLaunchKernelGGL((k_nn_wgrad<IO_EVEN, IO_FULL>), grid, block, 0, s, L, thin, in, grad, partial);
     else if (inm == IO_FULL && gm == IO_EVEN)
-        hipLaunchKernelGGL((k_nn_wgrad<CIN, COUT, IO_FULL, IO_EVEN>), grid, block, 0, s, L, thin, in, grad, partial);
+        hipLaunchKernelGGL((k_nn_wgrad<IO_FULL, IO_EVEN>), grid, block, 0, s, L, thin, in, grad, partial);
     else
-        hipLaunchKernelGGL((k_nn_wgrad<CIN, COUT, IO_EVEN, IO_EVEN>), grid, block, 0, s, L, thin, in, grad, partial);
-    return nblk;
-}
-
-#define NN_CHANNEL_SWITCH(CI, CO, CALL)                                   \
-    switch ((CI) * 100 + (CO)) {                                          \
-        case 101: CALL(1, 1); break;                                      \
-        case 102: CALL(1, 2); break;                                      \
-        case 104: CALL(1, 4); break;                                      \
-        case 108: CALL(1, 8); break;                                      \
-        case 201: CALL(2, 1); break;                                      \
-        case 202: CALL(2, 2); break;                                      \
-        case 401: CALL(4, 1); break;                                      \
-        case 404: CALL(4, 4); break;                                      \
-        case 801: CALL(8, 1); break;                                      \
-        case 808: CALL(8, 8); break;                                      \
-        case 204: CALL(2, 4); break;                                      \
-        case 402: CALL(4, 2); break;                                      \
-        case 408: CALL(4, 8); break;                                      \
-        case 804: CALL(8, 4); break;                                      \
-        case 208: CALL(2, 8); break;                                      \
-        case 802: CALL(8, 2); break;                                      \
-        default: return HISQ_ERR_UNSUPPORTED;                            \
-    }
-
-bool nn_channels_supported(int c) { return c == 1 || c == 2 || c == 4 || c == 8; }
-
-int nn_layer(const NnGeom &G, const void *thin, int cin, int cout, int inm, int outm, const float *in, float *out,
-             const void *amat, hipStream_t s) {
-    const Lex L{{G.L[0], G.L[1], G.L[2], G.L[3]}, G.V};
-#define CALL_LAYER(A, B) layer_launch<A, B>(L, thin, inm, outm, in, out, (const __bf16 *)amat, s)
-    NN_CHANNEL_SWITCH(cin, cout, CALL_LAYER)
-#undef CALL_LAYER
-    HISQ_HIP_CHECK(hipGetLastError());
-    return HISQ_OK;
-}
-
-int nn_wgrad(const NnGeom &G, const void *thin, int cin, int cout, int inm, int gm, const float *in,
-             const float *grad, float *partial, double *gacc, hipStream_t s) {
-    const Lex L{{G.L[0], G.L[1], G.L[2], G.L[3]}, G.V};
-    int nblk = 0;
-#define CALL_WG(A, B) nblk = wgrad_launch<A, B>(L, thin, inm, gm, in, grad, partial, s)
-    NN_CHANNEL_SWITCH(cin, cout, CALL_WG)
-#undef CALL_WG
+        hipLaunchKernelGGL((k_nn_wgrad<IO_EVEN, IO_EVEN>), grid, block, 0, s, L, thin, in, grad, partial);
+    const int nent = 16 * (inm == IO_EVEN ? 16 : 80);
+    float *fold = partial + (size_t)grid_blocks(G.V) * 16 * 80;
+    hipLaunchKernelGGL(k_nn_wgrad_fold, dim3((nent + 255) / 256, NN_FOLD), dim3(256), 0, s, partial, nblk, nent, fold);
     const int n = cout * 9 * cin;
-    hipLaunchKernelGGL(k_nn_wgrad_reduce, dim3((n + 127) / 128), dim3(128), 0, s, partial, nblk, cin, cout, gacc);
+    hipLaunchKernelGGL(k_nn_wgrad_reduce, dim3((n + 127) / 128), dim3(128), 0, s, fold, inm, cin, cout, gacc);
     HISQ_HIP_CHECK(hipGetLastError());
     return HISQ_OK;
 }
 
-size_t nn_wgrad_partial_floats(const NnGeom &G, int cin) {
-    const int nblk = (G.V + NN_SITES * NN_WAVES - 1) / (NN_SITES * NN_WAVES);
-    return (size_t)nblk * 16 * 16 * ((9 * cin + 15) / 16);
-}
-
-size_t nn_amat_elems(int cin) { return (size_t)16 * kpad(cin); }
-
-void nn_build_amat(const double *W, int cin, int cout, bool transposed, void *amat, hipStream_t s) {
-    const int ci = transposed ? cout : cin;
-    const int n = 16 * kpad(ci);
-    hipLaunchKernelGGL(k_nn_build_amat, dim3((n + 255) / 256), dim3(256), 0, s, W, cin, cout, (int)transposed,
+void nn_build_amat(const double *W, int cin, int cout, bool transposed, int inm, void *amat, hipStream_t s) {
+    const int n = (int)nn_amat_elems(inm);
+    hipLaunchKernelGGL(k_nn_build_amat, dim3((n + 255) / 256), dim3(256), 0, s, W, cin, cout, (int)transposed, inm,
                        (__bf16 *)amat);
 }
 
 int nn_pack_thin(const NnGeom &G, const double *U, void *dst, hipStream_t s) {
-    const Lex L{{G.L[0], G.L[1], G.L[2], G.L[3]}, G.V};
-    hipLaunchKernelGGL(k_pack_thin, dim3((G.V + 255) / 256, 4), dim3(256), 0, s, L, U, dst);
+    const Lex L = lex_of(G);
+    unsigned *bad = (unsigned *)((char *)dst + nn_thin_bytes(G) - 256);
+    HISQ_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_pack_thin, dim3((G.V + 255) / 256, 4), dim3(256), 0, s, L, U, dst, bad);
     HISQ_HIP_CHECK(hipGetLastError());
+    unsigned hb = 0;
+    HISQ_HIP_CHECK(hipMemcpyAsync(&hb, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HISQ_HIP_CHECK(hipStreamSynchronize(s));
+    if (hb) {
+        set_error("thin links: an entry is not finite or exceeds the FP16 range (|x| >= 32768)");
+        return HISQ_ERR_INVALID;
+    }
     return HISQ_OK;
 }
-
-size_t nn_thin_bytes(const NnGeom &G) { return (size_t)((G.V + 63) / 64) * 2 * 9 * 1024; }
 
 void nn_loss_grad(int vh, const float *out, const float *v, float *gout, double *part, double *scal, int batch,
                   hipStream_t s) {

@@ -17,7 +17,9 @@ static NnGeom nn_geom(const hisq_gauge_s *g) {
     return G;
 }
 
-static size_t act_bytes(const NnGeom &G, int c) { return spinor_bytes(F32, G.V) * c; }
+// layer input modes: the first layer (and the adjoint of the last) reads the
+// one-channel even-site spinor, every other layer a hidden activation
+enum { MODE_HIDDEN = 0, MODE_EVEN = 1 };
 
 int nn_create(hisq_nn_s **out, hisq_gauge_s *g, int nlayers, const int *ch, const double *weights, hipStream_t s) {
     static std::atomic<unsigned long long> next_id{1};
@@ -27,27 +29,24 @@ int nn_create(hisq_nn_s **out, hisq_gauge_s *g, int nlayers, const int *ch, cons
     n->nlayers = nlayers;
     n->ch.assign(ch, ch + nlayers + 1);
     const NnGeom G = nn_geom(g);
-    size_t off = 0, aoff = 0, aoff_t = 0, act = 0, hid = 1, part = 0;
+    size_t off = 0, aoff = 0, aoff_t = 0;
     std::vector<size_t> aoff_tv;
     for (int l = 0; l < nlayers; ++l) {
         n->woff.push_back(off);
         off += 2 * 9 * (size_t)ch[l] * ch[l + 1];
         n->aoff.push_back(aoff);
-        aoff += nn_amat_elems(ch[l]);
+        aoff += nn_amat_elems(l == 0 ? MODE_EVEN : MODE_HIDDEN);
         aoff_tv.push_back(aoff_t);
-        aoff_t += nn_amat_elems(ch[l + 1]);
-        if (l + 1 < nlayers) {
-            act += act_bytes(G, ch[l + 1]);
-            hid = std::max(hid, (size_t)ch[l + 1]);
-        }
-        part = std::max(part, nn_wgrad_partial_floats(G, ch[l]));
+        aoff_t += nn_amat_elems(l == nlayers - 1 ? MODE_EVEN : MODE_HIDDEN);
     }
+    const size_t act = (size_t)(nlayers - 1) * nn_act_bytes(G);
+    const size_t part = nn_wgrad_partial_floats(G);
     n->aoff.insert(n->aoff.end(), aoff_tv.begin(), aoff_tv.end());  // [fwd offsets..., adjoint offsets...]
     n->nweights = off;
     int rc;
     if ((rc = n->w.alloc(off * 8)) || (rc = n->m.alloc(off * 8)) || (rc = n->v.alloc(off * 8)) ||
         (rc = n->g.alloc(off * 8)) || (rc = n->amat.alloc(aoff * 2)) || (rc = n->amat_t.alloc(aoff_t * 2)) ||
-        (rc = n->act.alloc(std::max<size_t>(act, 16))) || (rc = n->gbuf.alloc(2 * act_bytes(G, (int)hid))) ||
+        (rc = n->act.alloc(std::max<size_t>(act, 16))) || (rc = n->gbuf.alloc(2 * nn_act_bytes(G))) ||
         (rc = n->out.alloc(spinor_bytes(F32, G.V / 2))) || (rc = n->gout.alloc(spinor_bytes(F32, G.V / 2))) ||
         (rc = n->partial.alloc(part * 4)) || (rc = n->scal.alloc(8 * sizeof(double))) ||
         (rc = n->partd.alloc(sizeof(double) * ((G.V / 2 + 255) / 256 + 1)))) {
@@ -67,17 +66,16 @@ static void build_amats(hisq_nn_s *n, hipStream_t s) {
     const int L = n->nlayers;
     for (int l = 0; l < L; ++l) {
         const double *W = (const double *)n->w.p + n->woff[l];
-        nn_build_amat(W, n->ch[l], n->ch[l + 1], false, (__bf16 *)n->amat.p + n->aoff[l], s);
-        nn_build_amat(W, n->ch[l], n->ch[l + 1], true, (__bf16 *)n->amat_t.p + n->aoff[L + l], s);
+        nn_build_amat(W, n->ch[l], n->ch[l + 1], false, l == 0 ? MODE_EVEN : MODE_HIDDEN,
+                      (__bf16 *)n->amat.p + n->aoff[l], s);
+        nn_build_amat(W, n->ch[l], n->ch[l + 1], true, l == L - 1 ? MODE_EVEN : MODE_HIDDEN,
+                      (__bf16 *)n->amat_t.p + n->aoff[L + l], s);
     }
     n->amat_valid = true;
 }
 
-static float *act_of(hisq_nn_s *n, int l) {  // output of layer l-1 = input of layer l (l >= 1)
-    const NnGeom G = nn_geom(n->gauge);
-    size_t off = 0;
-    for (int k = 1; k < l; ++k) off += act_bytes(G, n->ch[k]);
-    return (float *)((char *)n->act.p + off);
+static void *act_of(hisq_nn_s *n, int l) {  // output of layer l-1 = input of layer l (l >= 1)
+    return (char *)n->act.p + (size_t)(l - 1) * nn_act_bytes(nn_geom(n->gauge));
 }
 
 // z = N(r): r and z even FP32 spinors (public layout)
@@ -92,12 +90,10 @@ int nn_forward(hisq_nn_s *n, const float *in, float *out, hipStream_t s) {
     const int L = n->nlayers;
     int rc;
     for (int l = 0; l < L; ++l) {
-        const float *src = l == 0 ? in : act_of(n, l);
-        float *dst = l == L - 1 ? out : act_of(n, l + 1);
-        const int inm = l == 0 ? 1 : 0, outm = l == L - 1 ? 1 : 0;
-        if ((rc = nn_layer(G, g->thin.p, n->ch[l], n->ch[l + 1], inm, outm, src, dst,
-                           (const __bf16 *)n->amat.p + n->aoff[l], s)))
-            return rc;
+        const void *src = l == 0 ? (const void *)in : act_of(n, l);
+        void *dst = l == L - 1 ? (void *)out : act_of(n, l + 1);
+        const int inm = l == 0 ? MODE_EVEN : MODE_HIDDEN, outm = l == L - 1 ? MODE_EVEN : MODE_HIDDEN;
+        if ((rc = nn_layer(G, g->thin.p, inm, outm, src, dst, (const __bf16 *)n->amat.p + n->aoff[l], s))) return rc;
     }
     return HISQ_OK;
 }
@@ -112,30 +108,28 @@ int nn_loss_grad_batch(hisq_nn_s *n, int batch, const float *av, const float *v,
     int rc;
     HISQ_HIP_CHECK(hipMemsetAsync(n->g.p, 0, n->nweights * 8, s));
     HISQ_HIP_CHECK(hipMemsetAsync(n->scal.p, 0, 8 * sizeof(double), s));
-    size_t hidden = 1;
-    for (int l = 1; l < L; ++l) hidden = std::max(hidden, (size_t)n->ch[l]);
-    float *gb[2] = {(float *)n->gbuf.p, (float *)((char *)n->gbuf.p + act_bytes(G, (int)hidden))};
+    void *gb[2] = {n->gbuf.p, (char *)n->gbuf.p + nn_act_bytes(G)};
     for (int i = 0; i < batch; ++i) {
         const float *avi = (const float *)((const char *)av + sb * i);
         const float *vi = (const float *)((const char *)v + sb * i);
         if ((rc = nn_forward(n, avi, (float *)n->out.p, s))) return rc;
         nn_loss_grad(vh, (const float *)n->out.p, vi, (float *)n->gout.p, (double *)n->partd.p, (double *)n->scal.p,
                      batch, s);
-        const float *gcur = (const float *)n->gout.p;
-        int gmode = 1;
+        const void *gcur = n->gout.p;
+        int gmode = MODE_EVEN;
         for (int l = L - 1; l >= 0; --l) {
-            const float *inl = l == 0 ? avi : act_of(n, l);
-            const int inm = l == 0 ? 1 : 0;
+            const void *inl = l == 0 ? (const void *)avi : act_of(n, l);
+            const int inm = l == 0 ? MODE_EVEN : MODE_HIDDEN;
             if ((rc = nn_wgrad(G, g->thin.p, n->ch[l], n->ch[l + 1], inm, gmode, inl, gcur, (float *)n->partial.p,
                                (double *)n->g.p + n->woff[l], s)))
                 return rc;
             if (l > 0) {
-                float *gn = gb[l & 1];
-                if ((rc = nn_layer(G, g->thin.p, n->ch[l + 1], n->ch[l], gmode, 0, gcur, gn,
+                void *gn = gb[l & 1];
+                if ((rc = nn_layer(G, g->thin.p, gmode, MODE_HIDDEN, gcur, gn,
                                    (const __bf16 *)n->amat_t.p + n->aoff[L + l], s)))
                     return rc;
                 gcur = gn;
-                gmode = 0;
+                gmode = MODE_HIDDEN;
             }
         }
     }
@@ -173,7 +167,7 @@ int hisq_nn_create(hisq_nn_t *out, hisq_gauge_t g, int nlayers, const int *chann
     if (channels[0] != 1 || channels[nlayers] != 1)
         return nfail(HISQ_ERR_INVALID, "the first and last channel counts must be 1");
     for (int l = 0; l <= nlayers; ++l)
-        if (!nn_channels_supported(channels[l])) return nfail(HISQ_ERR_UNSUPPORTED, "channel counts must be 1, 2, 4 or 8");
+        if (!nn_channels_supported(channels[l])) return nfail(HISQ_ERR_UNSUPPORTED, "channel counts must be in 1..8");
     std::lock_guard<std::mutex> lk(g->mu);
     return nn_create(out, g, nlayers, channels, weights, (hipStream_t)stream);
 }

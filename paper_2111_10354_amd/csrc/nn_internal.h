@@ -15,14 +15,17 @@ struct NnGeom {
 bool nn_channels_supported(int c);
 size_t nn_thin_bytes(const NnGeom &G);
 int nn_pack_thin(const NnGeom &G, const double *U, void *dst, hipStream_t s);
-size_t nn_amat_elems(int cin);
-void nn_build_amat(const double *W, int cin, int cout, bool transposed, void *amat, hipStream_t s);
-// inm / outm: 0 = all sites, C channels; 1 = even sites, one channel (public FP32 spinor)
-int nn_layer(const NnGeom &G, const void *thin, int cin, int cout, int inm, int outm, const float *in, float *out,
-             const void *amat, hipStream_t s);
-size_t nn_wgrad_partial_floats(const NnGeom &G, int cin);
-int nn_wgrad(const NnGeom &G, const void *thin, int cin, int cout, int inm, int gm, const float *in,
-             const float *grad, float *partial, double *gacc, hipStream_t s);
+// Hidden activations: BF16, 8 channels, 96 bytes per site (tiled by 64 sites).
+size_t nn_act_bytes(const NnGeom &G);
+// Layer input / output modes: 0 = hidden (all sites, BF16 units); 1 = one
+// channel on even sites as an FP32 public spinor.
+size_t nn_amat_elems(int inm);
+void nn_build_amat(const double *W, int cin, int cout, bool transposed, int inm, void *amat, hipStream_t s);
+int nn_layer(const NnGeom &G, const void *thin, int inm, int outm, const void *in, void *out, const void *amat,
+             hipStream_t s);
+size_t nn_wgrad_partial_floats(const NnGeom &G);
+int nn_wgrad(const NnGeom &G, const void *thin, int cin, int cout, int inm, int gm, const void *in, const void *grad,
+             float *partial, double *gacc, hipStream_t s);
 void nn_loss_grad(int vh, const float *out, const float *v, float *gout, double *part, double *scal, int batch,
                   hipStream_t s);
 void nn_adam(double *w, double *m, double *v, const double *g, int n, double lr, int step, hipStream_t s);
@@ -38,7 +41,7 @@ struct hisq_nn_s {
     hisq::DevBuf w, m, v, g;          // FP64 master weights, Adam moments, gradient
     hisq::DevBuf amat, amat_t;        // bf16 real-block matrices per layer (forward, adjoint)
     std::vector<size_t> aoff;         // element offsets into amat / amat_t
-    hisq::DevBuf act;                 // activations of the hidden layers (FP32, full lattice)
+    hisq::DevBuf act;                 // activations of the hidden layers (BF16 units, full lattice)
     hisq::DevBuf gbuf;                // back-propagated gradients (two hidden-size buffers)
     hisq::DevBuf out, gout, partial, scal, partd;
     int step = 0;

@@ -41,7 +41,8 @@ def apply_gpu(g, net, dims, r):
 
 
 @pytest.mark.parametrize("dims,channels", [((4, 4, 4, 4), (1, 8, 8, 1)), ((6, 4, 4, 8), (1, 4, 1)),
-                                           ((8, 8, 8, 8), (1, 8, 8, 1)), ((4, 6, 4, 4), (1, 2, 8, 1))])
+                                           ((8, 8, 8, 8), (1, 8, 8, 1)), ((4, 6, 4, 4), (1, 2, 8, 1)),
+                                           ((6, 6, 6, 6), (1, 3, 5, 1)), ((6, 4, 6, 6), (1, 8, 8, 8, 1))])
 def test_forward_matches_oracle(cuda_device, dims, channels):
     g, net, F, L, U, ws = setup(dims, channels)
     r = synth.gaussian_source(dims, 99, 1, parity=0)[0]
@@ -77,7 +78,7 @@ def test_gauge_covariance(cuda_device):
     g.close()
 
 
-@pytest.mark.parametrize("channels", [(1, 8, 8, 1), (1, 2, 1)])
+@pytest.mark.parametrize("channels", [(1, 8, 8, 1), (1, 2, 1), (1, 3, 7, 1)])
 def test_loss_and_gradient_match_oracle(cuda_device, channels):
     dims = (4, 4, 4, 6)
     g, net, F, L, U, ws = setup(dims, channels, seed=3, noise=0.3, scale_identity=0.5)
@@ -120,4 +121,17 @@ def test_training_reduces_loss(cuda_device):
     l1 = net.loss_grad(B, av, v_raw, want_grad=False)[0]
     assert np.isfinite(l1) and l1 < 0.8 * l0, (l0, l1, losses[::8])
     net.close()
+    g.close()
+
+
+def test_thin_links_out_of_fp16_range_rejected(cuda_device):
+    import torch
+    dims = (4, 4, 4, 4)
+    F, L, U = synth.hisq_links(dims, 99, 0.5, want_thin=True)
+    g = make_gauge(dims, F, L, precs=("fp64",))
+    bad = np.array(U)
+    bad[5, 2, 1, 1] = 1e6
+    with pytest.raises(Exception):
+        hisq().gauge_set_thin(g, torch.from_numpy(bad).cuda())
+    hisq().gauge_set_thin(g, torch.from_numpy(np.ascontiguousarray(U)).cuda())
     g.close()
