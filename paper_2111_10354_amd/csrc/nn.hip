@@ -108,16 +108,6 @@ __device__ __forceinline__ int site_of(const Lex &g, int idx) {
     }
 }
 
-// Workgroups are handed to the eight XCDs round-robin (block b to XCD b % 8),
-// and each XCD has its own L2.  Renumber blocks so that every XCD works on one
-// contiguous range of sites: the lattice neighbours of a block's sites then
-// sit in the same L2 (all but the outermost direction).  A bijection on
-// [0, nblk) for any nblk.
-__device__ __forceinline__ int xcd_block(int b, int nblk) {
-    const int q = nblk >> 3, rem = nblk & 7, r = b & 7, k = b >> 3;
-    return r < rem ? r * (q + 1) + k : rem * (q + 1) + (r - rem) * q + k;
-}
-
 // ------------------------------------------------------------------ thin links (FP16)
 template <int MU>
 __device__ __forceinline__ void load_link(const void *thin, int s, cx<float> w[9]) {
@@ -334,7 +324,7 @@ __global__ __launch_bounds__(64 * NN_WAVES) void k_nn_layer(Lex g, const void *t
     __shared__ float Of[NN_WAVES][NW_SITES][6];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, j = l >> 4;
     const int nsites = OUTM == IO_FULL ? g.V : g.V / 2;
-    const int base = (xcd_block(blockIdx.x, gridDim.x) * NN_WAVES + w) * NW_SITES;
+    const int base = (blockIdx.x * NN_WAVES + w) * NW_SITES;
     const int sl = l >> 1, h = l & 1;  // lane pair (site, half)
     const int idx = base + sl;
     const bool valid = idx < nsites;
@@ -411,7 +401,7 @@ __global__ __launch_bounds__(64 * NN_WAVES) void k_nn_wgrad(Lex g, const void *t
     __shared__ float Red[NN_WAVES][16][KC];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, j = l >> 4;
     const int nsites = GM == IO_FULL ? g.V : g.V / 2;
-    const int base = (xcd_block(blockIdx.x, gridDim.x) * NN_WAVES + w) * NW_SITES;
+    const int base = (blockIdx.x * NN_WAVES + w) * NW_SITES;
     const int sl = l >> 1, h = l & 1;
     const int idx = base + sl;
     const bool valid = idx < nsites;
