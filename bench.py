@@ -46,9 +46,10 @@ def encode(cb, prec):
     return layout.encode(cb, prec)
 
 
-def counter_traffic(dims):
+def counter_traffic(dims, compressed):
     """HBM bytes per launch of the headline kernel from the committed rocprofv3
-    counter summary, or None if the kernel sources changed since it was taken."""
+    counter summary, or None if the kernel sources or the link layout changed
+    since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"dslash_fp32_{'x'.join(map(str, dims))}.traffic.json")
     if not os.path.exists(path):
@@ -57,6 +58,8 @@ def counter_traffic(dims):
     csrc = os.path.join(ROOT, "paper_2111_10354_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, n), "rb").read() for n in ("dslash.hip", "hisq_internal.h", "pack.hip"))
     if hashlib.sha256(src).hexdigest() != rec.get("kernel_sources_sha256"):
+        return None
+    if bool(rec.get("long_links_compressed", False)) != bool(compressed):
         return None
     return rec["traffic_bytes_per_launch"] / 1e9  # GB, like `achieved`
 
@@ -87,6 +90,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip the preconditioner network training and FCG")
+    ap.add_argument("--c5-solve", action="store_true",
+                    help="only the 96^3x24, m=0.002, 4-RHS solve: chosen forms against plain FP64 CG (minutes)")
     ap.add_argument("--only-fp32", action="store_true", help="time only the headline kernel")
     ap.add_argument("--tune-cache", type=str, default=os.path.join(ROOT, "paper_2111_10354_amd", "tuning",
                                                                   "gfx950.jsonl"),
@@ -114,6 +119,9 @@ def main():
         sys.exit(2)
 
     import synth  # input generator only
+    if args.c5_solve:
+        print(json.dumps(run_c5_solve()), flush=True)
+        return
     dims = tuple(int(v) for v in args.dims.split(","))
     V = synth.volume(dims)
     vh = V // 2
@@ -139,20 +147,29 @@ def main():
     import torch
     from paper_2111_10354_amd import hisq
 
-    precs = ("fp32",) if args.only_fp32 else ("fp64", "fp32", "fp16s")
-    fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
-    g = hisq.Gauge(dims, fd, ld, precs)
-    torch.cuda.synchronize()
-    del fd, ld
-    torch.cuda.empty_cache()
-    log(f"gauge packed: {g.device_bytes() / 2**30:.1f} GiB of link copies")
+    # every precision is packed even when only FP32 is timed, so that the
+    # headline kernel's buffers sit where they sit in the default run
+    precs = ("fp64", "fp32", "fp16s")
     tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
-    t1 = time.time()
-    for p in precs:
-        for n in ((1,) if args.only_fp32 else (1, cfg["nrhs"])):
-            hisq.autotune(g, p, n, tune)
-    log(f"autotune ({'cache ' + tune if tune else 'no cache'}): {time.time() - t1:.1f}s; "
-        f"FP32 1-RHS shape {hisq.dslash_shape(g, 'fp32', 1, 0)}")
+
+    def make_gauge(full_links):
+        fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
+        gx = hisq.Gauge(dims, fd, ld, precs, full_links=full_links)
+        torch.cuda.synchronize()
+        del fd, ld
+        torch.cuda.empty_cache()
+        t1 = time.time()
+        for p in precs:
+            for n in (1, cfg["nrhs"]):
+                hisq.autotune(gx, p, n, tune)
+        log(f"gauge ({'links whole' if full_links else 'long links compressed' if gx.compressed else 'links whole'}): "
+            f"{gx.device_bytes() / 2**30:.1f} GiB; autotune ({'cache ' + tune if tune else 'no cache'}) "
+            f"{time.time() - t1:.1f}s; FP32 1-RHS shape {hisq.dslash_shape(gx, 'fp32', 1, 0)}")
+        return gx
+
+    # the headline kernel reads every link whole: its GB/s measures bandwidth
+    # efficiency on the full 1200 B/site; the compressed layout is timed below
+    g = make_gauge(True)
 
     cb, odd_sites = cb_gather(dims, chi, 1)
     even_sites = cb_gather(dims, chi, 0)[1]
@@ -162,8 +179,9 @@ def main():
         out = torch.empty(hisq.spinor_bytes(p, vh), dtype=torch.uint8, device="cuda")
         bufs[p] = (inp, out)
 
-    def algo_bytes(p, nrhs=1):
-        link = {"fp64": 8, "fp32": 4, "fp16s": 2}[p] * 16 * 18
+    def algo_bytes(p, nrhs=1, comp=False):
+        real = {"fp64": 8, "fp32": 4, "fp16s": 2}[p]
+        link = real * (8 * 18 + 8 * 12) + 4 if comp else real * 16 * 18
         spin = {"fp64": 48, "fp32": 24, "fp16s": 16}[p]
         return vh * (link + nrhs * 2 * spin)
 
@@ -187,29 +205,40 @@ def main():
     log(f"sampled parity (256 sites) FP32 vs oracle: rel L2 {perr:.2e}")
 
     variants = {"fp32": {"ms": ms, "gbs": gbs}}
-    if not args.only_fp32:
-        for p in ("fp64", "fp16s"):
+    shape = hisq.dslash_shape(g, "fp32", 1, 0)
+
+    def time_variants(gx, comp, suffix, skip_fp32):
+        for p in ("fp64", "fp32", "fp16s"):
+            if p == "fp32" and skip_fp32:
+                continue
             i2, o2 = bufs[p]
-            m2 = time_launches(lambda: hisq.dslash_eo(g, 0, p, i2, o2), max(10, args.steps // 2), 3)
-            variants[p] = {"ms": m2, "gbs": algo_bytes(p) / (m2 * 1e-3) / 1e9}
-            log(f"{p} Dslash: {m2:.3f} ms, {variants[p]['gbs']:.0f} GB/s")
+            m2 = time_launches(lambda: hisq.dslash_eo(gx, 0, p, i2, o2), max(10, args.steps // 2), 3)
+            variants[p + suffix] = {"ms": m2, "gbs": algo_bytes(p, comp=comp) / (m2 * 1e-3) / 1e9}
+            log(f"{p}{suffix} Dslash: {m2:.3f} ms, {variants[p + suffix]['gbs']:.0f} GB/s")
         # 4 RHS (the workload's batch) through the multi-RHS kernel
         n = cfg["nrhs"]
         srcs = synth.gaussian_source(dims, synth.CFG_IDS["c5"], n, parity=1, index0=1)
         for p in ("fp32", "fp16s"):
-            raw = np.concatenate([encode(cb_gather(dims, s, 1)[0], p) for s in srcs])
+            raw = np.concatenate([encode(cb_gather(dims, s_, 1)[0], p) for s_ in srcs])
             i4 = torch.from_numpy(raw).cuda()
             o4 = torch.empty(hisq.spinor_bytes(p, vh) * n, dtype=torch.uint8, device="cuda")
-            m4 = time_launches(lambda: hisq.dslash_multi_rhs(g, 0, p, n, i4, o4), max(10, args.steps // 2), 3)
-            variants[f"{p}_x{n}rhs"] = {"ms": m4, "gbs": algo_bytes(p, n) / (m4 * 1e-3) / 1e9,
-                                        "ms_per_rhs": m4 / n}
-            log(f"{p} x{n} RHS Dslash: {m4:.3f} ms ({m4 / n:.3f} ms/RHS), {variants[f'{p}_x{n}rhs']['gbs']:.0f} GB/s")
+            m4 = time_launches(lambda: hisq.dslash_multi_rhs(gx, 0, p, n, i4, o4), max(10, args.steps // 2), 3)
+            key = f"{p}_x{n}rhs{suffix}"
+            variants[key] = {"ms": m4, "gbs": algo_bytes(p, n, comp=comp) / (m4 * 1e-3) / 1e9, "ms_per_rhs": m4 / n}
+            log(f"{key} Dslash: {m4:.3f} ms ({m4 / n:.3f} ms/RHS), {variants[key]['gbs']:.0f} GB/s")
             del i4, o4
-        for k, v in variants.items():
-            v["gflops"] = FLOP_PER_SITE * vh * (4 if "x4" in k else 1) / (v["ms"] * 1e-3) / 1e9
-            v["frac_hbm_peak"] = v["gbs"] / HBM_PEAK_GBS
 
-    shape = hisq.dslash_shape(g, "fp32", 1, 0)
+    if not args.only_fp32:
+        time_variants(g, False, "", True)
+        # long links as two rows + determinant sign (the layout the solvers use)
+        g.close()
+        torch.cuda.empty_cache()
+        g = make_gauge(False)
+        if g.compressed:
+            time_variants(g, True, "_compressed", False)
+    for k, v in variants.items():
+        v["gflops"] = FLOP_PER_SITE * vh * (4 if "x4" in k else 1) / (v["ms"] * 1e-3) / 1e9
+        v["frac_hbm_peak"] = v["gbs"] / HBM_PEAK_GBS
     sweep = None
     if not (args.quick or args.no_sweep or args.only_fp32):
         del bufs
@@ -229,7 +258,7 @@ def main():
             t_tot += time.time() - t1
             reps += 1
         t_one = t_tot / reps
-        cpu = {"value": algo_bytes("fp64") / t_one / 1e9, "unit": "GB/s", "cores": nthr, "kind": "oracle",
+        cpu = {"value": algo_bytes("fp64", comp=False) / t_one / 1e9, "unit": "GB/s", "cores": nthr, "kind": "oracle",
                "sample": f"{reps} full single-parity FP64 Dslash applications on the same {dims} lattice "
                          f"({t_one:.2f} s each); GB/s counts the FP64 algorithmic bytes (2400 B/site)"}
         log(f"oracle: {t_one:.2f} s per Dslash = {cpu['value']:.2f} GB/s")
@@ -259,11 +288,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"HISQ single-parity Dslash, {'x'.join(map(str, dims))} lattice, FP32 links "
-                               f"and spinors, 1 RHS, seeded links (eps={cfg['eps']})",
+                               f"(all stored whole) and spinors, 1 RHS, seeded links (eps={cfg['eps']})",
+                   "long_links_compressed": False,
                    "dims": list(dims), "sites_per_parity": vh, "bytes_per_step": algo_bytes("fp32"),
                    "flop_per_site": FLOP_PER_SITE},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dims),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dims, False),
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "cpu_baseline": cpu,
         "parity_sample_rel_l2": perr,
@@ -289,13 +319,14 @@ def run_mrhs_sweep(hisq, torch, tune):
     g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp32", "fp16s"))
     del F, L
     srcs = synth.gaussian_source(dims, synth.CFG_IDS["c3"], 16, parity=1)
-    out = {"workload": f"{'x'.join(map(str, dims))} single-parity Dslash, N right-hand sides", "fp32": {},
-           "fp16s": {}}
+    out = {"workload": f"{'x'.join(map(str, dims))} single-parity Dslash, N right-hand sides",
+           "long_links_compressed": g.compressed, "fp32": {}, "fp16s": {}}
     for p in ("fp32", "fp16s"):
         raw = np.concatenate([encode(cb_gather(dims, s, 1)[0], p) for s in srcs])
         i16 = torch.from_numpy(raw).cuda()
         o16 = torch.empty_like(i16)
-        link = {"fp32": 1152, "fp16s": 576}[p]
+        real = {"fp32": 4, "fp16s": 2}[p]
+        link = real * (8 * 18 + 8 * 12) + 4 if g.compressed else real * 16 * 18
         spin = {"fp32": 24, "fp16s": 16}[p]
         for n in (1, 2, 4, 8, 16):
             hisq.autotune(g, p, n, tune)
@@ -426,6 +457,70 @@ def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
                                                      sv["fcg_untrained"]["iterations"], 4)
     ident.close()
     net.close()
+    g.close()
+    return out
+
+
+def run_c5_solve(plain_rhs=1):
+    """(D^+D + 4m^2) x = b on 96^3 x 24, m = 0.002, 4 Gaussian RHS, tol 1e-10 on the
+    FP64 true residual.  Plain form: FP64 CG one RHS at a time (timed on the
+    first `plain_rhs` RHS; the 4-RHS total is that time per RHS x 4, marked as
+    such).  Chosen forms: the 4 RHS batched through the multi-RHS Dslash with
+    FP32 or FP16S sloppy iterations and FP64 reliable updates."""
+    import torch
+    import synth
+    from paper_2111_10354_amd import hisq
+    c = synth.CONFIGS["c5"]
+    dims, mass, n = c["dims"], c["mass"], c["nrhs"]
+    vh = synth.volume(dims) // 2
+    t0 = time.time()
+    F, L = synth.hisq_links(dims, synth.CFG_IDS["c5"], c["eps"])
+    log(f"C5 solve: fields {dims} in {time.time() - t0:.1f}s")
+    fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
+    g = hisq.Gauge(dims, fd, ld, ("fp64", "fp32", "fp16s"))
+    torch.cuda.synchronize()
+    del fd, ld, F, L
+    torch.cuda.empty_cache()
+    tune = os.path.join(ROOT, "paper_2111_10354_amd", "tuning", "gfx950.jsonl")
+    for p in ("fp64", "fp32", "fp16s"):
+        for k in (1, n):
+            hisq.autotune(g, p, k, tune)
+    srcs = synth.gaussian_source(dims, synth.CFG_IDS["c5"], n, parity=0)
+    b = torch.from_numpy(np.concatenate([encode(cb_gather(dims, s_, 0)[0], "fp64") for s_ in srcs])).cuda()
+    sb = hisq.spinor_bytes("fp64", vh)
+    out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, {n} Gaussian RHS, tol 1e-10 (FP64 true residual)",
+           "long_links_compressed": g.compressed}
+    # plain form
+    per = []
+    for i in range(plain_rhs):
+        bi = b[i * sb:(i + 1) * sb]
+        x = torch.zeros_like(bi)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        rc, st = hisq.cg_solve(g, mass, 1, bi, x, hisq.solver_params(sloppy_prec="fp64", graph_chunk=25))
+        wall = time.time() - t1
+        per.append({"status": rc, "seconds": round(wall, 3), "iterations": st[0]["iterations"],
+                    "true_residual": st[0]["true_residual"]})
+        log(f"C5 plain FP64 RHS {i}: {wall:.1f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
+    mean = sum(r["seconds"] for r in per) / len(per)
+    out["plain_fp64"] = {"per_rhs": per, "seconds_per_rhs": round(mean, 3),
+                         "seconds_4rhs": round(mean * n, 3),
+                         "note": f"timed on {plain_rhs} of {n} RHS; total = per-RHS time x {n}"}
+    for name, sloppy in (("batched_mixed_fp32", "fp32"), ("batched_mixed_fp16s", "fp16s")):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        rc, st = hisq.cg_solve(g, mass, n, b, x, hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25))
+        wall = time.time() - t1
+        out[name] = {"status": rc, "seconds_4rhs": round(wall, 3), "seconds_per_rhs": round(wall / n, 3),
+                     "iterations": [s_["iterations"] for s_ in st],
+                     "true_residual": [s_["true_residual"] for s_ in st]}
+        log(f"C5 {name}: {wall:.1f} s for {n} RHS, iterations {[s_['iterations'] for s_ in st]}, "
+            f"worst true res {max(s_['true_residual'] for s_ in st):.2e}")
+    best = min(("batched_mixed_fp32", "batched_mixed_fp16s"),
+               key=lambda k: out[k]["seconds_4rhs"] if out[k]["status"] == 0 else 1e30)
+    out["chosen"] = best
+    out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds_4rhs"] / out[best]["seconds_4rhs"], 3)
     g.close()
     return out
 

@@ -75,6 +75,8 @@ extern "C" {
 /* Bit masks for hisq_gauge_create's prec_mask. */
 #define HISQ_PREC_MASK(p) (1u << (p))
 #define HISQ_PREC_MASK_ALL 7u
+/* Store every link whole, even when the long links could be compressed. */
+#define HISQ_LINKS_FULL (1u << 8)
 
 typedef struct hisq_gauge_s *hisq_gauge_t;
 typedef struct hisq_nn_s *hisq_nn_t;
@@ -96,13 +98,23 @@ size_t hisq_spinor_bytes(int prec, int64_t vh);
  *   fat, lng device, complex double [V][4][3][3] (row a, column b of
  *            U_mu(x) at ((lex*4 + mu)*3 + a)*3 + b), phases and boundary
  *            signs folded in.  Only read during the call.
- *   prec_mask which packed copies to build (HISQ_PREC_MASK bits).  FP16
- *            links need every entry below 2^14 in magnitude.
+ *   prec_mask which packed copies to build (HISQ_PREC_MASK bits), plus
+ *            optionally HISQ_LINKS_FULL.  FP16 links need every entry below
+ *            2^14 in magnitude.
+ * Gauge-field compression (the paper's D-slash, Sec. 3: store part of each
+ * link, recompute the rest from its unitarity): unless HISQ_LINKS_FULL is
+ * set, when every long link is unitary with determinant +1 or -1 (deviation
+ * at most 1e-12 in FP64) only its first two rows are stored and the kernels
+ * rebuild the third as det * conj(row0 x row1); the fat links stay whole.
+ * hisq_gauge_links_compressed() reports the choice.
  * On success *out receives the handle.  Errors: -1 bad dims / null pointers /
  * empty mask, -3 out of memory, -2 HIP failure.
  */
 int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
                       unsigned prec_mask, void *stream);
+
+/* 1 if the handle stores its long links compressed, 0 if whole, -1 for NULL. */
+int hisq_gauge_links_compressed(hisq_gauge_t g);
 
 /* Release the handle and everything it owns (NULL is accepted). */
 int hisq_gauge_destroy(hisq_gauge_t g);

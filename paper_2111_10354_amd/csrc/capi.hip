@@ -96,8 +96,9 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
     int rc = check_dims(dims);
     if (rc) return rc;
     if (!fat || !lng) return fail(HISQ_ERR_INVALID, "fat and long link pointers are required");
-    if (prec_mask == 0 || (prec_mask & ~HISQ_PREC_MASK_ALL))
-        return fail(HISQ_ERR_INVALID, "prec_mask must be a nonzero combination of HISQ_PREC_MASK bits");
+    if ((prec_mask & HISQ_PREC_MASK_ALL) == 0 || (prec_mask & ~(HISQ_PREC_MASK_ALL | HISQ_LINKS_FULL)))
+        return fail(HISQ_ERR_INVALID, "prec_mask must be a nonzero combination of HISQ_PREC_MASK bits "
+                                      "(plus optionally HISQ_LINKS_FULL)");
     hipStream_t s = (hipStream_t)stream;
     hisq_gauge_s *g = new (std::nothrow) hisq_gauge_s();
     if (!g) return fail(HISQ_ERR_OOM, "host allocation failed");
@@ -113,9 +114,25 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
         delete g;
         return rc;
     }
+    if (!(prec_mask & HISQ_LINKS_FULL)) {
+        // compress the long links when every one is unitary with det +-1
+        e = hipMemsetAsync(maxabs.p, 0, sizeof(float), s);
+        float defect = 1.f;
+        if (e == hipSuccess) {
+            launch_long_link_defect(g->geom, lng, (unsigned *)maxabs.p, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&defect, maxabs.p, sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(HISQ_ERR_HIP, std::string("long-link check: ") + hipGetErrorString(e));
+        }
+        g->compressed = defect <= 1e-12f;
+    }
     for (int f = 0; f < 3; ++f) {
         if (!(prec_mask & HISQ_PREC_MASK(f))) continue;
-        const size_t bytes = link_parity_bytes(f, g->geom.vh);
+        const size_t bytes = link_parity_bytes(f, g->geom.vh, g->compressed);
         if ((rc = g->links[f][0].alloc(bytes)) || (rc = g->links[f][1].alloc(bytes))) {
             delete g;
             return rc;
@@ -126,7 +143,7 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
             mb = (float *)maxabs.p;
         }
         if (e == hipSuccess)
-            rc = launch_pack_links(g->geom, f, fat, lng, g->links[f][0].p, g->links[f][1].p, mb, s);
+            rc = launch_pack_links(g->geom, f, fat, lng, g->links[f][0].p, g->links[f][1].p, mb, g->compressed, s);
         if (e != hipSuccess || rc) {
             delete g;
             return rc ? rc : fail(HISQ_ERR_HIP, hipGetErrorString(e));
@@ -160,6 +177,12 @@ int hisq_gauge_destroy(hisq_gauge_t g) {
     (void)hipDeviceSynchronize();
     delete g;
     return HISQ_OK;
+}
+
+int hisq_gauge_links_compressed(hisq_gauge_t g) {
+    int rc = check_handle(g);
+    if (rc) return rc;
+    return g->compressed ? 1 : 0;
 }
 
 int hisq_gauge_device_bytes(hisq_gauge_t g, size_t *bytes) {

@@ -55,8 +55,8 @@ __device__ __forceinline__ int site_of_thread(const Geom &g, int i, int order) {
     return ((t * g.L[2] + z) * tpp + p) * 64 + (i & 63);
 }
 
-template <int LF, int SI, int SO, int TILE, bool EPI>
-__global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Spinor<SI> in,
+template <int LF, int SI, int SO, int TILE, bool EPI, bool COMP>
+__global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restrict__ lptr, Spinor<SI> in,
                                                      Spinor<SO> out, Spinor<SI> y,
                                                      const double *__restrict__ diag,
                                                      double *__restrict__ partials,
@@ -88,24 +88,55 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, Links<LF> links, Sp
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][c] = {R(0), R(0)};
 
+        // acc += m * (neighbour of slot k), for every RHS of the tile
+        auto apply = [&](int k, const cx<R> *m) {
+            const int nbh = hop_index(g, sc, h, k >> 2, slot_dist(k & 3));
 #pragma unroll
-        for (int gi = 0; gi < 16 / G; ++gi) {
-            cx<R> w[9 * G];
-            links.load_group(gi, h, w);
+            for (int r = 0; r < TILE; ++r) {
+                if (TILE > 1 && r0 + r >= nrhs) break;
+                const Spinor<SI> src = in.rhs(r0 + r);
+                cx<R> v[3];
+                src.load(nbh, v);
 #pragma unroll
-            for (int sl = 0; sl < G; ++sl) {
-                const int k = gi * G + sl;
-                const int nbh = hop_index(g, sc, h, k >> 2, slot_dist(k & 3));
+                for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int r = 0; r < TILE; ++r) {
-                    if (TILE > 1 && r0 + r >= nrhs) break;
-                    const Spinor<SI> src = in.rhs(r0 + r);
-                    cx<R> v[3];
-                    src.load(nbh, v);
+                    for (int b = 0; b < 3; ++b) cmac(acc[r][a], m[3 * a + b], v[b]);
+            }
+        };
+        if constexpr (!COMP) {
+            const Links<LF> links{lptr};
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
+            for (int gi = 0; gi < 16 / G; ++gi) {
+                cx<R> w[9 * G];
+                links.load_group(gi, h, w);
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) cmac(acc[r][a], w[9 * sl + 3 * a + b], v[b]);
+                for (int sl = 0; sl < G; ++sl) apply(gi * G + sl, w + 9 * sl);
+            }
+        } else {
+            // fat slots whole; long slots from rows 0, 1 and the determinant sign
+            constexpr int MC = CompGeom<LF>::MC, NC = CompGeom<LF>::NC;
+            const LinksC<LF> cl{lptr, g.vh};
+            const unsigned sg = cl.signs(h);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                {
+                    cx<R> w[18 * MC];
+                    cl.load_fat(c, h, w);
+#pragma unroll
+                    for (int s2 = 0; s2 < 2 * MC; ++s2) apply(4 * (c * MC + (s2 >> 1)) + (s2 & 1), w + 9 * s2);
+                }
+                {
+                    cx<R> lr[12 * MC];
+                    cl.load_long(c, h, lr);
+#pragma unroll
+                    for (int s2 = 0; s2 < 2 * MC; ++s2) {
+                        const int mu = c * MC + (s2 >> 1), bit = 2 * mu + (s2 & 1);
+                        cx<R> m[9];
+#pragma unroll
+                        for (int e = 0; e < 6; ++e) m[e] = lr[6 * s2 + e];
+                        rebuild_row2(m, ((sg >> bit) & 1u) ? R(-1) : R(1));
+                        apply(4 * mu + 2 + (s2 & 1), m);
+                    }
                 }
             }
         }
@@ -164,12 +195,15 @@ template <int LF, int SI, int SO, int TILE, bool EPI>
 static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     dim3 block(a.block);
     dim3 grid(dslash_grid_blocks(g, a.block), (a.nrhs + TILE - 1) / TILE);
-    Links<LF> L{a.links};
     Spinor<SI> in = spinor_view<SI>(const_cast<void *>(a.in), g.vh);
     Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
     Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);
-    hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI>), grid, block, 0, s, g, L, in, out, y,
-                       a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+    if (a.compressed)
+        hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, true>), grid, block, 0, s, g, a.links, in, out, y,
+                           a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+    else
+        hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, false>), grid, block, 0, s, g, a.links, in, out, y,
+                           a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
 }
 
 template <int LF, int SI, int SO, bool EPI>

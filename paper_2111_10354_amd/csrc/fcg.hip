@@ -455,10 +455,10 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
         stats->true_residual = rel;
         stats->wall_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         stats->dslash_bytes =
-            (double)fcg_iters * (double)(dslash_algorithmic_bytes(F32, F32, F32, vh, 1, false) +
-                                         dslash_algorithmic_bytes(F32, F32, F32, vh, 1, true)) +
-            (double)(fcg_ru + 1) * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false) +
-                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true)) +
+            (double)fcg_iters * (double)(dslash_algorithmic_bytes(F32, F32, F32, vh, 1, false, g->compressed) +
+                                         dslash_algorithmic_bytes(F32, F32, F32, vh, 1, true, g->compressed)) +
+            (double)(fcg_ru + 1) * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
+                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed)) +
             cg_st.dslash_bytes;
     }
     return status;

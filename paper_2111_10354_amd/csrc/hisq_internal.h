@@ -209,8 +209,29 @@ template <> struct LinkGroup<F32> { static constexpr int G = 2; };
 template <> struct LinkGroup<H16> { static constexpr int G = 4; };
 
 inline int link_group_size(int f) { return f == F64 ? 1 : f == F32 ? 2 : 4; }
-inline size_t link_parity_bytes(int f, int64_t vh) {
+
+// Compressed layout (the gauge-field compression of the D-slash: only part of
+// a link is stored and the rest recomputed from its unitarity).  Used when
+// every long link is unitary with determinant +1 or -1: slots j = 2, 3 keep
+// rows 0 and 1, and row 2 = det * conj(row 0 x row 1) is rebuilt in the
+// kernel; the fat links (not unitary in general) stay whole.  The sites of a
+// 64-site tile are stored chunk by chunk; chunk c covers MC directions
+// mu = c MC .. c MC + MC - 1 and holds first the fat slots (mu, j = 0, 1 for
+// each mu of the chunk, 9 complex entries each) and then the long slots
+// (mu, j = 2, 3, rows 0 and 1 = 6 complex entries each), entries row-major,
+// slots in that order, packed into 16-byte units:
+//   byte offset of (site h, chunk c, unit e) = (((h / 64) * NC + c) * UC + e) * 1024 + (h % 64) * 16
+//   FP64: MC 1, NC 4, 18 fat + 12 long units;  FP32: MC 1, NC 4, 9 + 6;  FP16: MC 2, NC 2, 9 + 6.
+// After the last tile, one 32-bit word per site holds the determinant signs:
+// bit 2 mu + (j - 2) set when the determinant of slot (mu, j) is -1.
+template <int F> struct CompGeom { static constexpr int MC = 1, NC = 4, UF = 18, UL = 12; };
+template <> struct CompGeom<F32> { static constexpr int MC = 1, NC = 4, UF = 9, UL = 6; };
+template <> struct CompGeom<H16> { static constexpr int MC = 2, NC = 2, UF = 9, UL = 6; };
+__host__ __device__ inline int comp_units_per_site(int f) { return f == F64 ? 120 : 60; }  // NC * (UF + UL)
+
+inline size_t link_parity_bytes(int f, int64_t vh, bool compressed = false) {
     const int64_t tiles = (vh + LINK_TILE - 1) / LINK_TILE;
+    if (compressed) return (size_t)tiles * (comp_units_per_site(f) * 1024 + LINK_TILE * 4);
     return (size_t)tiles * (16 / link_group_size(f)) * 9 * 1024;
 }
 
@@ -263,6 +284,106 @@ template <> struct Links<H16> {
     }
 };
 
+// Loaders of the compressed layout: fat part (2 MC slots, 9 entries each) and
+// long part (2 MC slots, rows 0 and 1 = 6 entries each) of chunk c.
+template <int F> struct LinksC;
+
+template <int F>
+__device__ __forceinline__ const u4v *comp_unit_ptr(const void *base, int c, int h) {
+    constexpr int NC = CompGeom<F>::NC, UC = CompGeom<F>::UF + CompGeom<F>::UL;
+    return (const u4v *)base + ((size_t)((h >> 6) * NC + c) * UC) * 64 + (h & 63);
+}
+
+template <int F>
+__device__ __forceinline__ unsigned comp_signs(const void *base, int vh, int h) {
+    const size_t tiles = (size_t)(vh + LINK_TILE - 1) / LINK_TILE;
+    const unsigned *sg = (const unsigned *)((const char *)base + tiles * comp_units_per_site(F) * 1024);
+    return __builtin_nontemporal_load(sg + h);
+}
+
+template <> struct LinksC<F64> {
+    const void *p;
+    int vh;
+    __device__ __forceinline__ unsigned signs(int h) const { return comp_signs<F64>(p, vh, h); }
+    __device__ __forceinline__ void load_fat(int c, int h, cx<double> w[18]) const {
+        const u4v *b = comp_unit_ptr<F64>(p, c, h);
+#pragma unroll
+        for (int e = 0; e < 18; ++e) {
+            d2v a = __builtin_bit_cast(d2v, __builtin_nontemporal_load(b + e * 64));
+            w[e] = {a.x, a.y};
+        }
+    }
+    __device__ __forceinline__ void load_long(int c, int h, cx<double> r[12]) const {
+        const u4v *b = comp_unit_ptr<F64>(p, c, h) + 18 * 64;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            d2v a = __builtin_bit_cast(d2v, __builtin_nontemporal_load(b + e * 64));
+            r[e] = {a.x, a.y};
+        }
+    }
+};
+
+template <> struct LinksC<F32> {
+    const void *p;
+    int vh;
+    __device__ __forceinline__ unsigned signs(int h) const { return comp_signs<F32>(p, vh, h); }
+    __device__ __forceinline__ void load_fat(int c, int h, cx<float> w[18]) const {
+        const u4v *b = comp_unit_ptr<F32>(p, c, h);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            f4v a = __builtin_bit_cast(f4v, __builtin_nontemporal_load(b + e * 64));
+            w[2 * e] = {a.x, a.y};
+            w[2 * e + 1] = {a.z, a.w};
+        }
+    }
+    __device__ __forceinline__ void load_long(int c, int h, cx<float> r[12]) const {
+        const u4v *b = comp_unit_ptr<F32>(p, c, h) + 9 * 64;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            f4v a = __builtin_bit_cast(f4v, __builtin_nontemporal_load(b + e * 64));
+            r[2 * e] = {a.x, a.y};
+            r[2 * e + 1] = {a.z, a.w};
+        }
+    }
+};
+
+template <> struct LinksC<H16> {
+    const void *p;
+    int vh;
+    __device__ __forceinline__ unsigned signs(int h) const { return comp_signs<H16>(p, vh, h); }
+    __device__ __forceinline__ void load_fat(int c, int h, cx<float> w[36]) const {
+        const u4v *b = comp_unit_ptr<H16>(p, c, h);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const h8v a = __builtin_bit_cast(h8v, __builtin_nontemporal_load(b + e * 64));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[4 * e + q] = {(float)a[2 * q], (float)a[2 * q + 1]};
+        }
+    }
+    __device__ __forceinline__ void load_long(int c, int h, cx<float> r[24]) const {
+        const u4v *b = comp_unit_ptr<H16>(p, c, h) + 9 * 64;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const h8v a = __builtin_bit_cast(h8v, __builtin_nontemporal_load(b + e * 64));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[4 * e + q] = {(float)a[2 * q], (float)a[2 * q + 1]};
+        }
+    }
+};
+
+// Row 2 of a unitary matrix with determinant d = +-1 from rows 0 and 1:
+// m[6..8] = d * conj(row0 x row1).
+template <class R>
+__device__ __forceinline__ void rebuild_row2(cx<R> m[9], R d) {
+    const cx<R> *a = m, *b = m + 3;
+    const cx<R> c0 = cmul(a[1], b[2]), c1 = cmul(a[2], b[1]);
+    const cx<R> c2 = cmul(a[2], b[0]), c3 = cmul(a[0], b[2]);
+    const cx<R> c4 = cmul(a[0], b[1]), c5 = cmul(a[1], b[0]);
+    m[6] = {d * (c0.re - c1.re), -d * (c0.im - c1.im)};
+    m[7] = {d * (c2.re - c3.re), -d * (c2.im - c3.im)};
+    m[8] = {d * (c4.re - c5.re), -d * (c4.im - c5.im)};
+}
+
 // ------------------------------------------------------------------ errors
 void set_error(const std::string &msg);
 const char *get_error();
@@ -279,7 +400,11 @@ const char *get_error();
 // ------------------------------------------------------------------ launch wrappers
 // Link packing: canonical [V][4][3][3] complex double -> packed per parity.
 int launch_pack_links(const Geom &g, int fmt, const double *fat, const double *lng, void *dst_even,
-                      void *dst_odd, float *maxabs_dev, hipStream_t s);
+                      void *dst_odd, float *maxabs_dev, bool compressed, hipStream_t s);
+// Largest deviation of any long link from a unitary matrix with determinant
+// +-1 (max |L L^+ - 1| entry or | det - round(det) |), into *defect_bits as
+// float bits (atomic max; zero it first).
+void launch_long_link_defect(const Geom &g, const double *lng, unsigned *defect_bits, hipStream_t s);
 
 struct CgState;
 
@@ -300,6 +425,7 @@ struct DslashLaunch {
     int tile;
     int block;
     int order;  // tile processing order (0 memory order, 1 t-fastest planes)
+    int compressed;  // links in the compressed layout
 };
 int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s);
 bool order_supported(const Geom &g, int order);

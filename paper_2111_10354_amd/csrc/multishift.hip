@@ -292,8 +292,8 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
             o.iterations = (k == 0 ? iters_total : hm[k].iters) + rs[k].iterations;
             o.wall_ms = total_ms;
             o.reliable_updates = rs[k].reliable_updates;
-            o.dslash_bytes = (double)iters_total * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false) +
-                                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true)) /
+            o.dslash_bytes = (double)iters_total * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
+                                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed)) /
                                  ns +
                              rs[k].dslash_bytes;
             stats[order[k]] = o;

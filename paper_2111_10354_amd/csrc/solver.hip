@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "solver_internal.h"
@@ -45,8 +47,8 @@ int DevBuf::alloc(size_t n) {
 
 static size_t real_bytes(int f) { return f == F64 ? 8 : f == F32 ? 4 : 2; }
 
-size_t dslash_algorithmic_bytes(int fl, int fi, int fo, int64_t vh, int nrhs, bool epi) {
-    const size_t links = 16 * 18 * real_bytes(fl);
+size_t dslash_algorithmic_bytes(int fl, int fi, int fo, int64_t vh, int nrhs, bool epi, bool comp) {
+    const size_t links = comp ? (8 * 18 + 8 * 12) * real_bytes(fl) + 4 : 16 * 18 * real_bytes(fl);
     const size_t per_rhs = spinor_bytes(fi, 1) + spinor_bytes(fo, 1) + (epi ? spinor_bytes(fi, 1) : 0);
     return (size_t)vh * (links + (size_t)nrhs * per_rhs);
 }
@@ -88,6 +90,7 @@ int gauge_dslash(hisq_gauge_s *g, int out_parity, int fl, int fi, int fo, int nr
     a.tile = sh.tile;
     a.block = sh.block;
     a.order = sh.order;
+    a.compressed = g->compressed ? 1 : 0;
     return launch_dslash(g->geom, a, s);
 }
 
@@ -263,10 +266,25 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     HISQ_HIP_CHECK(hipGetLastError());
 
     // iterate
+    // HISQ_SOLVER_TRACE=1 prints the progress every 2000 iterations to stderr
+    static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
+    int next_report = 2000;
     const long max_chunks = (long)prm.max_iter / chunk + 2 * (prm.max_iter / std::max(1, prm.ru_period)) + 16;
     for (long c = 0; c < max_chunks; ++c) {
         HISQ_HIP_CHECK(hipMemcpyAsync(hs.data(), w.state.p, sizeof(CgState) * n, hipMemcpyDeviceToHost, s));
         HISQ_HIP_CHECK(hipStreamSynchronize(s));
+        if (trace) {
+            int it = 0;
+            double worst = 0.0;
+            for (int i = 0; i < n; ++i) {
+                it = std::max(it, hs[i].iter);
+                if (hs[i].flag != CG_DONE) worst = std::max(worst, std::sqrt(std::max(hs[i].rho, 0.0) / b2[i]));
+            }
+            if (it >= next_report) {
+                std::fprintf(stderr, "[cg] iter %d, %d RHS, worst iterated |r|/|b| %.3e\n", it, n, worst);
+                next_report = (it / 2000 + 1) * 2000;
+            }
+        }
         bool attention = false, running = false;
         for (auto &c2 : hs) {
             attention |= c2.flag == CG_ATTENTION;
@@ -311,11 +329,11 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
             o.true_residual = tr;
             o.wall_ms = ms;
             o.dslash_bytes = (double)c.iter *
-                                 (double)(dslash_algorithmic_bytes(S, S, S, vh, 1, false) +
-                                          dslash_algorithmic_bytes(S, S, S == H16 ? F32 : S, vh, 1, true)) +
+                                 (double)(dslash_algorithmic_bytes(S, S, S, vh, 1, false, g->compressed) +
+                                          dslash_algorithmic_bytes(S, S, S == H16 ? F32 : S, vh, 1, true, g->compressed)) +
                              (double)(c.reliable + 1) *
-                                 (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false) +
-                                          dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true));
+                                 (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
+                                          dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed));
         }
     }
     return worst;

@@ -118,8 +118,9 @@ struct hisq_gauge_s {
     hisq::Geom geom;
     int device = 0;
     hisq::DevBuf links[3][2];  // [format][output parity]
+    bool compressed = false;   // long links stored as two rows + determinant sign
     hisq::DevBuf diag_buf;     // epilogue coefficients for hisq_dslash_multi_rhs
-    hisq::DevBuf thin;         // thin links (FP32) for the preconditioner network
+    hisq::DevBuf thin;         // thin links (FP16) for the preconditioner network
     hipStream_t capture_stream = nullptr;
     std::mutex mu;
     // autotuned shapes keyed by (links fmt, in fmt, out fmt, nrhs, epilogue)
@@ -143,7 +144,9 @@ int nb_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int n, bool epi);
 // Time the candidate launch shapes (or read them from `cache`) and install the best.
 int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, const char *cache, hipStream_t s,
                 DslashShape *chosen, double *chosen_ms);
-size_t dslash_algorithmic_bytes(int fmt_links, int fmt_in, int fmt_out, int64_t vh, int nrhs, bool epi);
+// Algorithmic bytes of one Dslash launch (links read once, spinors once per RHS);
+// comp: long links in the compressed layout (two rows + determinant-sign word).
+size_t dslash_algorithmic_bytes(int fmt_links, int fmt_in, int fmt_out, int64_t vh, int nrhs, bool epi, bool comp);
 
 int cg_solve(hisq_gauge_s *g, double mass, int nrhs, const double *b, double *x, const double *sigma,
              const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);

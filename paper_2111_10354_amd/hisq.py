@@ -76,6 +76,7 @@ def _load():
         "hisq_nn_loss_grad": (C.c_int, [vp, C.c_int, vp, vp, dp, dp, vp]),
         "hisq_nn_train_step": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, dp, vp]),
         "hisq_dslash_shape": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]),
+        "hisq_gauge_links_compressed": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -92,7 +93,9 @@ EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_c
            "hisq_solver_params_default", "hisq_cg_solve", "hisq_multishift_cg", "hisq_precond_apply",
            "hisq_autotune", "hisq_dslash_shape", "hisq_gauge_set_thin", "hisq_nn_create", "hisq_nn_destroy",
            "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
-           "hisq_nn_train_step")
+           "hisq_nn_train_step", "hisq_gauge_links_compressed")
+
+LINKS_FULL = 1 << 8  # hisq_gauge_create: store every link whole
 
 
 def last_error() -> str:
@@ -142,7 +145,7 @@ class Gauge:
     """Handle owning the packed link copies (see hisq_gauge_create)."""
 
     def __init__(self, dims, fat: torch.Tensor, lng: torch.Tensor, precs=("fp64", "fp32", "fp16s"),
-                 stream=None):
+                 stream=None, full_links: bool = False):
         self.dims = tuple(int(d) for d in dims)
         V = 1
         for d in self.dims:
@@ -154,10 +157,17 @@ class Gauge:
         mask = 0
         for p in precs:
             mask |= 1 << _prec(p)
+        if full_links:
+            mask |= LINKS_FULL
         h = C.c_void_p()
         d = (C.c_int * 4)(*self.dims)
         _check(LIB.hisq_gauge_create(C.byref(h), d, _ptr(fat), _ptr(lng), mask, _stream(stream)))
         self.handle = h
+
+    @property
+    def compressed(self) -> bool:
+        """True if the long links are stored as two rows (see hisq_gauge_create)."""
+        return bool(_check(LIB.hisq_gauge_links_compressed(self.handle), allow_soft=True))
 
     def device_bytes(self) -> int:
         n = C.c_size_t()

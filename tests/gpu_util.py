@@ -26,10 +26,10 @@ def device_links(F, L):
     return torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
 
 
-def make_gauge(dims, F, L, precs=("fp64", "fp32", "fp16s")):
+def make_gauge(dims, F, L, precs=("fp64", "fp32", "fp16s"), full_links=False):
     import torch
     f, l = device_links(F, L)
-    g = hisq().Gauge(dims, f, l, precs)
+    g = hisq().Gauge(dims, f, l, precs, full_links=full_links)
     torch.cuda.synchronize()
     del f, l
     return g

@@ -6,7 +6,10 @@ Tolerances (relative L2 over the output vector):
   arithmetic): 2e-3 -- 2^-12 relative rounding of every link entry and of the
   output, summed over 16 terms, stays near 3e-4; the bar leaves margin.
 The oracle is fed exactly the (rounded) input the GPU received, so the error
-measured is that of the kernel and of the link/output storage only.
+measured is that of the kernel and of the link/output storage only.  Every
+case runs with the long links compressed (two rows stored, the third rebuilt
+from unitarity; the default for the unitary Naik links of the workloads) and
+with all links stored whole.
 """
 
 import numpy as np
@@ -22,7 +25,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-13, "fp32": 1e-6, "fp16s": 2e-3}
 
 # several tiles and a ragged tail (Vh = 480, 960), one exact multiple (2048),
-# and enough workgroups for the XCD-aware block order to engage (4096, 6144)
+# and a few thousand sites (4096, 6144)
 DIMS = [(4, 4, 4, 4), (6, 4, 4, 10), (10, 6, 4, 8), (8, 8, 8, 8), (16, 8, 8, 8), (8, 12, 8, 16)]
 
 
@@ -30,11 +33,11 @@ DIMS = [(4, 4, 4, 4), (6, 4, 4, 10), (10, 6, 4, 8), (8, 8, 8, 8), (16, 8, 8, 8),
 def gauges(cuda_device):
     cache = {}
 
-    def get(dims, apbc=False, free=None):
-        key = (dims, apbc, free)
+    def get(dims, apbc=False, free=None, full=False):
+        key = (dims, apbc, free, full)
         if key not in cache:
             F, L = fields(dims, apbc=apbc, free=free)
-            cache[key] = (make_gauge(dims, F, L), F, L)
+            cache[key] = (make_gauge(dims, F, L, full_links=full), F, L)
         return cache[key]
 
     yield get
@@ -55,16 +58,50 @@ def run_dslash(g, dims, F, L, chi_full, parity, prec):
     return got, want
 
 
+@pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
 @pytest.mark.parametrize("dims", DIMS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 @pytest.mark.parametrize("parity", [0, 1])
-def test_dslash_matches_oracle(gauges, dims, prec, parity):
-    flush(f"dslash parity dims={dims} prec={prec} parity={parity}")
-    g, F, L = gauges(dims, apbc=(dims[3] % 4 == 2))
+def test_dslash_matches_oracle(gauges, dims, prec, parity, full):
+    flush(f"dslash parity dims={dims} prec={prec} parity={parity} full={full}")
+    g, F, L = gauges(dims, apbc=(dims[3] % 4 == 2), full=full)
+    assert g.compressed == (not full)
     chi = synth.gaussian_source(dims, 99, 1, parity=1 - parity, index0=parity)[0]
     got, want = run_dslash(g, dims, F, L, chi, parity, prec)
     err = rel_l2(got, want)
     assert err <= TOL[prec], err
+
+
+def test_compression_choice(gauges, cuda_device):
+    """Long links are compressed exactly when every one is unitary with det +-1."""
+    import torch
+    dims = (4, 4, 4, 4)
+    g, F, L = gauges(dims)
+    assert g.compressed
+    g2, _, _ = gauges(dims, apbc=True)
+    assert g2.compressed  # boundary signs make det = -1, still compressible
+    gf, _, _ = gauges(dims, free=(9 / 8, -1 / 24))
+    assert not gf.compressed  # L = c3 eta: not unitary
+    L2 = np.array(L)
+    L2[17, 2] *= 1.0 + 1e-9  # one long link slightly off the unitary group
+    gp = make_gauge(dims, F, L2)
+    assert not gp.compressed
+    chi = synth.gaussian_source(dims, 99, 1, parity=1)[0]
+    got, want = run_dslash(gp, dims, F, L2, chi, 0, "fp64")
+    assert rel_l2(got, want) <= TOL["fp64"]
+    gp.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_compressed_matches_full(gauges, prec):
+    """Same input through both layouts: equal up to the storage rounding of the third row."""
+    dims = (10, 6, 4, 8)
+    gc, F, L = gauges(dims)
+    gw, _, _ = gauges(dims, full=True)
+    chi = synth.gaussian_source(dims, 99, 1, parity=0, index0=3)[0]
+    a, _ = run_dslash(gc, dims, F, L, chi, 1, prec)
+    b, _ = run_dslash(gw, dims, F, L, chi, 1, prec)
+    assert rel_l2(a, b) <= TOL[prec], rel_l2(a, b)
 
 
 def test_fp16s_error_against_unrounded_input(gauges):
