@@ -91,7 +91,9 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-nn", action="store_true", help="skip the preconditioner network training and FCG")
     ap.add_argument("--c5-solve", action="store_true",
-                    help="only the 96^3x24, m=0.002, 4-RHS solve: chosen forms against plain FP64 CG (minutes)")
+                    help="only the 96^3x24, m=0.002, 4-RHS solve: chosen form against plain FP64 CG (minutes)")
+    ap.add_argument("--c5-fp16s", action="store_true",
+                    help="with --c5-solve: also the FP16S-sloppy batched solve (~10 minutes at this mass)")
     ap.add_argument("--only-fp32", action="store_true", help="time only the headline kernel")
     ap.add_argument("--tune-cache", type=str, default=os.path.join(ROOT, "paper_2111_10354_amd", "tuning",
                                                                   "gfx950.jsonl"),
@@ -120,7 +122,7 @@ def main():
 
     import synth  # input generator only
     if args.c5_solve:
-        print(json.dumps(run_c5_solve()), flush=True)
+        print(json.dumps(run_c5_solve(with_fp16s=args.c5_fp16s)), flush=True)
         return
     dims = tuple(int(v) for v in args.dims.split(","))
     V = synth.volume(dims)
@@ -181,7 +183,7 @@ def main():
 
     def algo_bytes(p, nrhs=1, comp=False):
         real = {"fp64": 8, "fp32": 4, "fp16s": 2}[p]
-        link = real * (8 * 18 + 8 * 12) + 4 if comp else real * 16 * 18
+        link = real * (8 * 18 + 8 * 12) + 4 if comp and p != "fp64" else real * 16 * 18
         spin = {"fp64": 48, "fp32": 24, "fp16s": 16}[p]
         return vh * (link + nrhs * 2 * spin)
 
@@ -209,8 +211,8 @@ def main():
 
     def time_variants(gx, comp, suffix, skip_fp32):
         for p in ("fp64", "fp32", "fp16s"):
-            if p == "fp32" and skip_fp32:
-                continue
+            if (p == "fp32" and skip_fp32) or (p == "fp64" and comp):
+                continue  # the FP64 copy always keeps its links whole
             i2, o2 = bufs[p]
             m2 = time_launches(lambda: hisq.dslash_eo(gx, 0, p, i2, o2), max(10, args.steps // 2), 3)
             variants[p + suffix] = {"ms": m2, "gbs": algo_bytes(p, comp=comp) / (m2 * 1e-3) / 1e9}
@@ -461,7 +463,7 @@ def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
     return out
 
 
-def run_c5_solve(plain_rhs=1):
+def run_c5_solve(plain_rhs=1, with_fp16s=False):
     """(D^+D + 4m^2) x = b on 96^3 x 24, m = 0.002, 4 Gaussian RHS, tol 1e-10 on the
     FP64 true residual.  Plain form: FP64 CG one RHS at a time (timed on the
     first `plain_rhs` RHS; the 4-RHS total is that time per RHS x 4, marked as
@@ -506,7 +508,8 @@ def run_c5_solve(plain_rhs=1):
     out["plain_fp64"] = {"per_rhs": per, "seconds_per_rhs": round(mean, 3),
                          "seconds_4rhs": round(mean * n, 3),
                          "note": f"timed on {plain_rhs} of {n} RHS; total = per-RHS time x {n}"}
-    for name, sloppy in (("batched_mixed_fp32", "fp32"), ("batched_mixed_fp16s", "fp16s")):
+    forms = (("batched_mixed_fp32", "fp32"),) + ((("batched_mixed_fp16s", "fp16s"),) if with_fp16s else ())
+    for name, sloppy in forms:
         x = torch.zeros_like(b)
         torch.cuda.synchronize()
         t1 = time.time()
@@ -517,8 +520,7 @@ def run_c5_solve(plain_rhs=1):
                      "true_residual": [s_["true_residual"] for s_ in st]}
         log(f"C5 {name}: {wall:.1f} s for {n} RHS, iterations {[s_['iterations'] for s_ in st]}, "
             f"worst true res {max(s_['true_residual'] for s_ in st):.2e}")
-    best = min(("batched_mixed_fp32", "batched_mixed_fp16s"),
-               key=lambda k: out[k]["seconds_4rhs"] if out[k]["status"] == 0 else 1e30)
+    best = min((f for f, _ in forms), key=lambda k: out[k]["seconds_4rhs"] if out[k]["status"] == 0 else 1e30)
     out["chosen"] = best
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds_4rhs"] / out[best]["seconds_4rhs"], 3)
     g.close()

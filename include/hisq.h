@@ -104,16 +104,17 @@ size_t hisq_spinor_bytes(int prec, int64_t vh);
  * Gauge-field compression (the paper's D-slash, Sec. 3: store part of each
  * link, recompute the rest from its unitarity): unless HISQ_LINKS_FULL is
  * set, when every long link is unitary with determinant +1 or -1 (deviation
- * at most 1e-12 in FP64) only its first two rows are stored and the kernels
- * rebuild the third as det * conj(row0 x row1); the fat links stay whole.
- * hisq_gauge_links_compressed() reports the choice.
+ * at most 1e-12 in FP64) the FP32 and FP16 copies store only its first two
+ * rows and the kernels rebuild the third as det * conj(row0 x row1).  The fat
+ * links, and every link of the FP64 copy (which carries the true residual),
+ * stay whole.  hisq_gauge_links_compressed() reports the choice.
  * On success *out receives the handle.  Errors: -1 bad dims / null pointers /
  * empty mask, -3 out of memory, -2 HIP failure.
  */
 int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
                       unsigned prec_mask, void *stream);
 
-/* 1 if the handle stores its long links compressed, 0 if whole, -1 for NULL. */
+/* 1 if the handle's FP32 / FP16 long links are compressed, 0 if whole, -1 for NULL. */
 int hisq_gauge_links_compressed(hisq_gauge_t g);
 
 /* Release the handle and everything it owns (NULL is accepted). */

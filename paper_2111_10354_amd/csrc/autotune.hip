@@ -69,7 +69,7 @@ static std::string arch_name(int dev) {
 static std::string tune_key(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi) {
     std::ostringstream k;
     k << arch_name(g->device) << "|" << fl << fi << fo << "|" << g->dims[0] << "x" << g->dims[1] << "x" << g->dims[2]
-      << "x" << g->dims[3] << "|n" << nrhs << "|e" << (int)epi << (g->compressed ? "|c" : "");
+      << "x" << g->dims[3] << "|n" << nrhs << "|e" << (int)epi << (links_compressed(g, fl) ? "|c" : "");
     return k.str();
 }
 
@@ -160,7 +160,7 @@ int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, con
         a.tile = sh.tile;
         a.block = sh.block;
         a.order = sh.order;
-        a.compressed = g->compressed ? 1 : 0;
+        a.compressed = links_compressed(g, fl) ? 1 : 0;
         return launch_dslash(G, a, s);
     };
 

@@ -94,11 +94,15 @@ __global__ void k_reduce_true(const double *__restrict__ part, int nb, CgState *
         S.since_ru = 0;
         if (!finite(rr)) {
             S.flag = CG_BREAKDOWN;
-        } else if (rr <= S.stop2) {
+        } else if (rr <= S.true2) {
             S.flag = CG_DONE;
         } else if (S.iter >= S.max_iter) {
             S.flag = CG_MAXITER;
         } else {
+            // the iterated residual claimed convergence but the true one has not
+            // followed: aim the iterated residual lower (halve its target), or the
+            // solve would crawl along the tolerance one reliable update at a time
+            if (S.rho_new <= S.stop2) S.stop2 *= 0.25;
             // resume: the p update of this iteration uses the recomputed residual
             S.rho_new = rr;
             S.beta = rr / S.rho;
@@ -118,7 +122,7 @@ __global__ void k_reduce_init(const double *__restrict__ part, int nb, CgState *
         S.rho = rr;
         if (!finite(rr)) {
             S.flag = CG_BREAKDOWN;
-        } else if (rr <= S.stop2) {
+        } else if (rr <= S.true2) {
             S.flag = CG_DONE;
         } else {
             S.flag = CG_RUNNING;

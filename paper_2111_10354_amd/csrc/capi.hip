@@ -132,7 +132,7 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
     }
     for (int f = 0; f < 3; ++f) {
         if (!(prec_mask & HISQ_PREC_MASK(f))) continue;
-        const size_t bytes = link_parity_bytes(f, g->geom.vh, g->compressed);
+        const size_t bytes = link_parity_bytes(f, g->geom.vh, links_compressed(g, f));
         if ((rc = g->links[f][0].alloc(bytes)) || (rc = g->links[f][1].alloc(bytes))) {
             delete g;
             return rc;
@@ -143,7 +143,8 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
             mb = (float *)maxabs.p;
         }
         if (e == hipSuccess)
-            rc = launch_pack_links(g->geom, f, fat, lng, g->links[f][0].p, g->links[f][1].p, mb, g->compressed, s);
+            rc = launch_pack_links(g->geom, f, fat, lng, g->links[f][0].p, g->links[f][1].p, mb,
+                                   links_compressed(g, f), s);
         if (e != hipSuccess || rc) {
             delete g;
             return rc ? rc : fail(HISQ_ERR_HIP, hipGetErrorString(e));

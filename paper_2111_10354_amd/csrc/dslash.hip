@@ -198,10 +198,13 @@ static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     Spinor<SI> in = spinor_view<SI>(const_cast<void *>(a.in), g.vh);
     Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
     Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);
-    if (a.compressed)
-        hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, true>), grid, block, 0, s, g, a.links, in, out, y,
-                           a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
-    else
+    if constexpr (LF != F64) {  // FP64 links are always stored whole
+        if (a.compressed) {
+            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, true>), grid, block, 0, s, g, a.links, in, out,
+                               y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+            return;
+        }
+    }
         hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, false>), grid, block, 0, s, g, a.links, in, out, y,
                            a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
 }

@@ -347,7 +347,8 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
     static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
     FcgState hs;
     std::memset(&hs, 0, sizeof(hs));
-    hs.cg.stop2 = prm.tol * prm.tol * b2;
+    hs.cg.stop2 = prm.tol * prm.tol * b2;  // iterated-residual trigger (tightened below)
+    hs.cg.true2 = hs.cg.stop2;             // target of the true residual
     hs.cg.ru_period = std::max(1, prm.ru_period);
     hs.cg.max_iter = prm.max_iter;
     // host checks between chunks land on periodic reliable updates: the chunk
@@ -388,7 +389,10 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
             fallback = broke = true;
             break;
         }
-        if (tr <= hs.cg.stop2) break;
+        if (tr <= hs.cg.true2) break;
+        // the iterated residual claimed convergence but the true one has not
+        // followed: aim the iterated residual lower
+        if (!first && hs.rr <= hs.cg.stop2) hs.cg.stop2 *= 0.25;
         if (tr < 0.5 * best_true) {
             best_true = tr;
             stagnant = 0;

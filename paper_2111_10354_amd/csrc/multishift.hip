@@ -189,6 +189,7 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     CgState hb;
     std::memset(&hb, 0, sizeof(hb));
     hb.stop2 = prm.tol * prm.tol * b2;
+    hb.true2 = hb.stop2;
     hb.max_iter = prm.max_iter;
     hb.flag = CG_ATTENTION;
     std::vector<MsState> hm(ns);

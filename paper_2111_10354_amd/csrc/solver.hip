@@ -48,7 +48,7 @@ int DevBuf::alloc(size_t n) {
 static size_t real_bytes(int f) { return f == F64 ? 8 : f == F32 ? 4 : 2; }
 
 size_t dslash_algorithmic_bytes(int fl, int fi, int fo, int64_t vh, int nrhs, bool epi, bool comp) {
-    const size_t links = comp ? (8 * 18 + 8 * 12) * real_bytes(fl) + 4 : 16 * 18 * real_bytes(fl);
+    const size_t links = (comp && fl != F64) ? (8 * 18 + 8 * 12) * real_bytes(fl) + 4 : 16 * 18 * real_bytes(fl);
     const size_t per_rhs = spinor_bytes(fi, 1) + spinor_bytes(fo, 1) + (epi ? spinor_bytes(fi, 1) : 0);
     return (size_t)vh * (links + (size_t)nrhs * per_rhs);
 }
@@ -90,7 +90,7 @@ int gauge_dslash(hisq_gauge_s *g, int out_parity, int fl, int fi, int fo, int nr
     a.tile = sh.tile;
     a.block = sh.block;
     a.order = sh.order;
-    a.compressed = g->compressed ? 1 : 0;
+    a.compressed = links_compressed(g, fl) ? 1 : 0;
     return launch_dslash(g->geom, a, s);
 }
 
@@ -239,6 +239,7 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
         CgState &c = hs[i];
         std::memset(&c, 0, sizeof(c));
         c.stop2 = prm.tol * prm.tol * b2[i];
+        c.true2 = c.stop2;
         c.ru_period = (S == F64) ? 0 : std::max(1, prm.ru_period);
         c.max_iter = prm.max_iter;
         c.flag = CG_ATTENTION;

@@ -27,7 +27,8 @@ struct CgState {
     double rho_new;  // <r, r> after the last update
     double pap;      // Re <p, A p>
     double alpha, beta;
-    double stop2;    // (tol |b|)^2
+    double stop2;    // iterated-residual trigger for the true-residual check, starts at (tol |b|)^2
+    double true2;    // target of the FP64 true residual, (tol |b|)^2
     double true_rr;  // last |b - A x|^2 computed in FP64
     int iter;        // completed iterations
     int since_ru;    // iterations since the last reliable update
@@ -118,7 +119,7 @@ struct hisq_gauge_s {
     hisq::Geom geom;
     int device = 0;
     hisq::DevBuf links[3][2];  // [format][output parity]
-    bool compressed = false;   // long links stored as two rows + determinant sign
+    bool compressed = false;   // FP32 / FP16 long links stored as two rows + determinant sign
     hisq::DevBuf diag_buf;     // epilogue coefficients for hisq_dslash_multi_rhs
     hisq::DevBuf thin;         // thin links (FP16) for the preconditioner network
     hipStream_t capture_stream = nullptr;
@@ -131,6 +132,12 @@ struct hisq_gauge_s {
 };
 
 namespace hisq {
+
+// The FP64 copy always keeps every link whole: it carries the true residual
+// and the reliable updates, where a 1e-15 row-rebuild error times the
+// condition number (up to ~1e6 at the lightest masses) would reach the 1e-10
+// target.  The sloppy FP32 / FP16 copies are compressed when possible.
+inline bool links_compressed(const hisq_gauge_s *g, int fmt) { return g->compressed && fmt != F64; }
 
 DslashShape pick_shape(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi);
 

@@ -166,7 +166,7 @@ class Gauge:
 
     @property
     def compressed(self) -> bool:
-        """True if the long links are stored as two rows (see hisq_gauge_create)."""
+        """True if the FP32 / FP16 long links are stored as two rows (see hisq_gauge_create)."""
         return bool(_check(LIB.hisq_gauge_links_compressed(self.handle), allow_soft=True))
 
     def device_bytes(self) -> int:
