@@ -227,7 +227,16 @@ inline int link_group_size(int f) { return f == F64 ? 1 : f == F32 ? 2 : 4; }
 template <int F> struct CompGeom { static constexpr int MC = 1, NC = 4, UF = 18, UL = 12; };
 template <> struct CompGeom<F32> { static constexpr int MC = 1, NC = 4, UF = 9, UL = 6; };
 template <> struct CompGeom<H16> { static constexpr int MC = 2, NC = 2, UF = 9, UL = 6; };
-__host__ __device__ inline int comp_units_per_site(int f) { return f == F64 ? 120 : 60; }  // NC * (UF + UL)
+// 16-byte units per site (per 64-site tile, in units of 1 KiB) = NC * (UF + UL)
+template <int F>
+__host__ __device__ constexpr int comp_units() {
+    return CompGeom<F>::NC * (CompGeom<F>::UF + CompGeom<F>::UL);
+}
+__host__ __device__ inline int comp_units_per_site(int f) {
+    return f == F64 ? comp_units<F64>() : f == F32 ? comp_units<F32>() : comp_units<H16>();
+}
+static_assert(comp_units<F64>() == 120 && comp_units<F32>() == 60 && comp_units<H16>() == 30,
+              "compressed layouts: 15 or 30 units per direction chunk");
 
 inline size_t link_parity_bytes(int f, int64_t vh, bool compressed = false) {
     const int64_t tiles = (vh + LINK_TILE - 1) / LINK_TILE;
