@@ -6,6 +6,8 @@
 #include <cstring>
 #include <new>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "solver_internal.h"
 
 namespace hisq {
@@ -59,6 +61,9 @@ static int check_params(const hisq_solver_params &p) {
 
 using namespace hisq;
 
+TraceRange::TraceRange(const char *name) { roctxRangePush(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
+
 hisq_gauge_s::~hisq_gauge_s() {
     cg_ws.clear();
     fcg_ws.reset();
@@ -91,6 +96,7 @@ void hisq_solver_params_default(hisq_solver_params *p) {
 
 int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
                       unsigned prec_mask, void *stream) {
+    TraceRange tr_("hisq_gauge_create");
     if (!out) return fail(HISQ_ERR_INVALID, "out is NULL");
     *out = nullptr;
     int rc = check_dims(dims);
@@ -238,6 +244,7 @@ int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, co
 
 int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double *x,
                   const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
+    TraceRange tr_("hisq_cg_solve");
     int rc = check_handle(g);
     if (rc) return rc;
     hisq_solver_params prm;
@@ -267,6 +274,7 @@ int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double
 
 int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *shifts, const double *b,
                        double *x, const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
+    TraceRange tr_("hisq_multishift_cg");
     int rc = check_handle(g);
     if (rc) return rc;
     hisq_solver_params prm;
@@ -287,6 +295,7 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
 }
 
 int hisq_autotune(hisq_gauge_t g, int prec, int nrhs, const char *cache_path, void *stream) {
+    TraceRange tr_("hisq_autotune");
     int rc = check_handle(g);
     if (rc) return rc;
     if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");

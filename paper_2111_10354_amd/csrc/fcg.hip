@@ -309,6 +309,7 @@ static int fcg_run_chunk(hisq_gauge_s *g, hisq_nn_s *net, FcgWorkspace &w, int c
 
 int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hisq_solver_params &prm,
               hisq_solver_stats *stats, hipStream_t s) {
+    TraceRange tr_("flexible CG");
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     hisq_nn_s *net = (hisq_nn_s *)prm.precond;

@@ -393,6 +393,16 @@ __device__ __forceinline__ void rebuild_row2(cx<R> m[9], R d) {
     m[8] = {d * (c4.re - c5.re), -d * (c4.im - c5.im)};
 }
 
+// ------------------------------------------------------------------ tracing
+// roctx range over a scope: solver phases show up in `rocprofv3 --marker-trace`
+// (no-ops when no profiler is attached).
+struct TraceRange {
+    explicit TraceRange(const char *name);
+    ~TraceRange();
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // ------------------------------------------------------------------ errors
 void set_error(const std::string &msg);
 const char *get_error();

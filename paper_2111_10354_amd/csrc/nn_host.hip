@@ -204,6 +204,7 @@ int hisq_nn_set_weights(hisq_nn_t net, const double *weights, void *stream) {
 
 int hisq_nn_loss_grad(hisq_nn_t net, int batch, const void *av, const void *v, double *loss, double *grad,
                       void *stream) {
+    TraceRange tr_("hisq_nn_loss_grad");
     if (!net || !av || !v || batch < 1) return nfail(HISQ_ERR_INVALID, "net, av, v and batch >= 1 are required");
     if (!net->gauge->thin.p) return nfail(HISQ_ERR_UNSUPPORTED, "the gauge handle has no thin links");
     hipStream_t s = (hipStream_t)stream;
@@ -220,6 +221,7 @@ int hisq_nn_loss_grad(hisq_nn_t net, int batch, const void *av, const void *v, d
 
 int hisq_nn_train_step(hisq_nn_t net, int batch, const void *av, const void *v, double lr, double *loss,
                        void *stream) {
+    TraceRange tr_("hisq_nn_train_step");
     if (!net || !av || !v || batch < 1 || !(lr > 0.0))
         return nfail(HISQ_ERR_INVALID, "net, av, v, batch >= 1 and lr > 0 are required");
     if (!net->gauge->thin.p) return nfail(HISQ_ERR_UNSUPPORTED, "the gauge handle has no thin links");

@@ -149,6 +149,7 @@ static int apply_A64(hisq_gauge_s *g, CgWorkspace &w, const void *x, void *ax, h
 
 // Reliable update for RHS flagged CG_ATTENTION.
 static int cg_reliable(hisq_gauge_s *g, CgWorkspace &w, hipStream_t s) {
+    TraceRange tr_("cg reliable update");
     const int S = w.fmt, n = w.n, vh = g->geom.vh;
     int rc;
     if (S != F64) launch_accum_zero(F32, vh, n, w.x64.p, w.xs.p, w.st(), CG_ATTENTION, s);

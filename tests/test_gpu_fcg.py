@@ -200,3 +200,57 @@ def test_trained_network_gain(lat):
     flush(f"iterations: flexible CG + trained network {st[0]['iterations']}, plain CG {st2[0]['iterations']}")
     assert st[0]["iterations"] <= 1.5 * st2[0]["iterations"]
     net.close()
+
+
+def test_checkpoint_restores_the_network(lat, tmp_path):
+    """Weights saved after training and loaded into a fresh network give the
+    same preconditioner output bit for bit."""
+    import torch
+    from paper_2111_10354_amd import checkpoint
+    dims, F, L, U, g = lat
+    net = make_net(g, (1, 4, 1), seed=3, noise=0.2, scale=0.2)
+    vs = synth.gaussian_source(dims, 99, 2, parity=0, index0=400)
+    raw = to_device(np.concatenate([encode(to_cb(dims, v, 0), "fp32") for v in vs]))
+    for _ in range(3):
+        net.train_step(2, raw, raw, 1e-3)
+    checkpoint.save(str(tmp_path / "n"), net.get_weights(), (1, 4, 1), dims=dims, steps=3)
+    w, h = checkpoint.load(str(tmp_path / "n"))
+    net2 = hisq().Net(g, tuple(h["channels"]), w)
+    half = raw.numel() // 2
+    a, b = torch.empty_like(raw[:half]), torch.empty_like(raw[:half])
+    hisq().precond_apply(g, net, raw[:half], a)
+    hisq().precond_apply(g, net2, raw[:half], b)
+    assert torch.equal(a, b)
+    net.close()
+    net2.close()
+
+
+def test_nan_network_falls_back(lat):
+    """A network that returns NaN (corrupted weights) breaks the flexible CG,
+    which hands the solve to plain FP64 CG."""
+    dims, F, L, U, g = lat
+    net = make_net(g, (1, 2, 1))
+    w = net.get_weights()
+    w[3] = np.nan
+    net.set_weights(w)
+    b = synth.gaussian_source(dims, 99, 1, parity=0, index0=13)[0]
+    rc, st, (x,) = fcg(g, dims, 0.1, [b], net)
+    assert rc == 3 and st[0]["fallback_used"] == 1, st
+    check_solution(dims, F, L, 0.1, b, x, st[0])
+    net.close()
+
+
+def test_solver_failure_statuses(lat):
+    """Host-forced failures end every kernel normally and come back as statuses."""
+    import torch
+    dims, F, L, U, g = lat
+    b = synth.gaussian_source(dims, 99, 1, parity=0, index0=14)[0]
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    x = torch.zeros_like(bd)
+    rc, st = hisq().cg_solve(g, 0.1, 1, bd, x, hisq().solver_params(max_iter=1))
+    assert rc == 1 and st[0]["status"] == 1 and st[0]["iterations"] <= 1
+    bad = bd.clone()
+    bad.view(torch.float64)[5] = float("nan")
+    x.zero_()
+    rc, st = hisq().cg_solve(g, 0.1, 1, bad, x, hisq().solver_params(sloppy_prec="fp32"))
+    assert rc in (1, 2) and st[0]["status"] in (1, 2), st
