@@ -105,11 +105,36 @@ static void cache_append(const char *path, const std::string &key, const DslashS
     f << buf;
 }
 
+// Candidate traversal orders: memory order, t-fastest planes, and, for window
+// budgets of 1, 2 and 4 MiB (one XCD's L2 holds 4 MiB, shared with the link
+// stream), the XCD-brick column whose seven-t-slice window of input spinors
+// (a tile of RHS) fits the budget with the fewest face re-reads 6/BY + 6/BZ.
+static std::vector<int> brick_orders(const Geom &G, int fi, int tile) {
+    std::vector<int> o{0, 1};
+    const double site_b = (fi == F64 ? 48.0 : fi == F32 ? 24.0 : 16.0) * tile;
+    for (double budget : {1.0, 2.0, 4.0}) {
+        int best = -1;
+        double best_cost = 1e30;
+        for (int by = 1; by <= std::min(G.L[1], 255); ++by)
+            for (int bz = 1; bz <= std::min(G.L[2], 255); ++bz) {
+                if (G.L[1] % by || G.L[2] % bz || (G.lxh * by) % 64) continue;
+                if (7.0 * G.lxh * by * bz * site_b > budget * 1024 * 1024) continue;
+                const double cost = 6.0 / by + 6.0 / bz;
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best = 2 | by << 8 | bz << 16;
+                }
+            }
+        if (best >= 0 && std::find(o.begin(), o.end(), best) == o.end()) o.push_back(best);
+    }
+    return o;
+}
+
 static bool valid_shape(const Geom &geom, int fl, int nrhs, const DslashShape &s) {
     if (s.tile < 1 || s.tile > 8 || (s.tile & (s.tile - 1)) || s.tile > std::max(1, nrhs)) return false;
     if (fl == F64 && s.tile > 4) return false;
     if (s.block != 64 && s.block != 128 && s.block != 256) return false;
-    return order_supported(geom, s.order);
+    return order_supported(geom, s.order, s.block);
 }
 
 int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, const char *cache, hipStream_t s,
@@ -173,7 +198,7 @@ int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, con
     std::vector<DslashShape> cands;
     for (int tile : {1, 2, 4, 8})
         for (int block : {64, 128, 256})
-            for (int order : {0, 1}) {
+            for (int order : brick_orders(G, fi, tile)) {
                 DslashShape c;
                 c.tile = tile;
                 c.block = block;

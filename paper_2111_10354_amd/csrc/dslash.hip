@@ -40,19 +40,46 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Processing order of the 64-site tiles.  order 0: memory order (x, y, z, t).
-// order 1: (z, t) planes with t fastest, which brings the time-direction
-// neighbours 16x closer in processing order (a win once several RHS make the
-// gathered spinors a large share of the traffic).  Needs whole tiles per plane.
-__device__ __forceinline__ int site_of_thread(const Geom &g, int i, int order) {
-    // grid tail: keep it out of range (the permutation below would map an
+// Processing order of the 64-site tiles (the low byte of `order`).
+//
+// 0: memory order (x, y, z, t).
+// 1: (z, t) planes with t fastest, which brings the time-direction neighbours
+//    16x closer in processing order.  Needs whole tiles per plane.
+// 2: XCD bricks.  Workgroup b runs on XCD b % 8 (workgroups are dealt to the
+//    eight XCDs in turn), so logical block (b % 8) * nb/8 + b/8 hands every XCD
+//    one contiguous eighth of the processing order and its own L2 sees every
+//    neighbour gather of that eighth.  The order walks columns of BY y-rows by
+//    BZ z-planes (BY = bits 8-15 of `order`, BZ = bits 16-23), with z-block
+//    slowest, then y-block, then t, then z inside the block, then the column's
+//    tiles.  While a column is swept along t, all sixteen hops of the sites in
+//    flight (+-1 and +-3 in every direction) fall inside a window of seven
+//    t-slices of the column, which is sized to stay in one L2; only the column
+//    faces are fetched twice.
+__device__ __forceinline__ int site_of_thread(const Geom &g, int blk, int nb, int tid, int order) {
+    const int kind = order & 0xff;
+    if (kind == 2) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    const int i = blk * (int)blockDim.x + tid;
+    // grid tail: keep it out of range (the permutations below would map an
     // index past the last tile back onto a valid one)
-    if (order == 0 || i >= g.vh) return i;
+    if (kind == 0 || i >= g.vh) return i;
     const int tpp = (g.lxh * g.L[1]) >> 6;  // tiles per (z, t) plane
-    const int wt = i >> 6;
-    const int q = wt / tpp, p = wt - q * tpp;
-    const int z = q / g.L[3], t = q - z * g.L[3];
-    return ((t * g.L[2] + z) * tpp + p) * 64 + (i & 63);
+    int wt = i >> 6;
+    if (kind == 1) {
+        const int q = wt / tpp, p = wt - q * tpp;
+        const int z = q / g.L[3], t = q - z * g.L[3];
+        return ((t * g.L[2] + z) * tpp + p) * 64 + (i & 63);
+    }
+    const int by = (order >> 8) & 0xff, bz = (order >> 16) & 0xff;
+    const int ty = (g.lxh * by) >> 6;  // tiles per column row block
+    const int nyb = g.L[1] / by;
+    const int within = wt % ty;
+    wt /= ty;
+    const int zz = wt % bz;
+    wt /= bz;
+    const int t = wt % g.L[3];
+    wt /= g.L[3];
+    const int yb = wt % nyb, zb = wt / nyb;
+    return ((t * g.L[2] + zb * bz + zz) * tpp + yb * ty + within) * 64 + (i & 63);
 }
 
 template <int LF, int SI, int SO, int TILE, bool EPI, bool COMP>
@@ -66,7 +93,7 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
     constexpr int G = LinkGroup<LF>::G;
     const int nb = gridDim.x;
     const int blk = blockIdx.x;
-    const int h = site_of_thread(g, blk * blockDim.x + threadIdx.x, order);
+    const int h = site_of_thread(g, blk, nb, threadIdx.x, order);
     const int r0 = blockIdx.y * TILE;
     if (skip) {
         bool idle = true;
@@ -93,8 +120,11 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
             const int nbh = hop_index(g, sc, h, k >> 2, slot_dist(k & 3));
 #pragma unroll
             for (int r = 0; r < TILE; ++r) {
-                if (TILE > 1 && r0 + r >= nrhs) break;
-                const Spinor<SI> src = in.rhs(r0 + r);
+                // a ragged last tile repeats its last RHS (those results are
+                // never stored): no branch, so the compiler can issue the
+                // gathers of every RHS of the tile before the first one returns
+                const int rr = (TILE > 1 && r0 + r >= nrhs) ? nrhs - 1 : r0 + r;
+                const Spinor<SI> src = in.rhs(rr);
                 cx<R> v[3];
                 src.load(nbh, v);
 #pragma unroll
@@ -103,22 +133,32 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                     for (int b = 0; b < 3; ++b) cmac(acc[r][a], m[3 * a + b], v[b]);
             }
         };
+        // One RHS: every slot unrolled, the compiler interleaves the loads of
+        // neighbouring slots.  Several RHS: one link group (or compressed
+        // chunk) per loop trip with the gathers of all its RHS in flight
+        // together; unrolled, the compiler hoists every gather of the site and
+        // spills them to scratch.
         if constexpr (!COMP) {
             const Links<LF> links{lptr};
-#pragma unroll
-            for (int gi = 0; gi < 16 / G; ++gi) {
+            auto group = [&](int gi) {
                 cx<R> w[9 * G];
                 links.load_group(gi, h, w);
 #pragma unroll
                 for (int sl = 0; sl < G; ++sl) apply(gi * G + sl, w + 9 * sl);
+            };
+            if constexpr (TILE == 1) {
+#pragma unroll
+                for (int gi = 0; gi < 16 / G; ++gi) group(gi);
+            } else {
+#pragma unroll 1
+                for (int gi = 0; gi < 16 / G; ++gi) group(gi);
             }
         } else {
             // fat slots whole; long slots from rows 0, 1 and the determinant sign
             constexpr int MC = CompGeom<LF>::MC, NC = CompGeom<LF>::NC;
             const LinksC<LF> cl{lptr, g.vh};
             const unsigned sg = cl.signs(h);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
+            auto chunk = [&](int c) {
                 {
                     cx<R> w[18 * MC];
                     cl.load_fat(c, h, w);
@@ -138,6 +178,13 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                         apply(4 * mu + 2 + (s2 & 1), m);
                     }
                 }
+            };
+            if constexpr (TILE == 1) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) chunk(c);
+            } else {
+#pragma unroll 1
+                for (int c = 0; c < NC; ++c) chunk(c);
             }
         }
 
@@ -230,8 +277,19 @@ static int launch_epi(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     return a.diag ? launch_tile<LF, SI, SO, true>(g, a, s) : launch_tile<LF, SI, SO, false>(g, a, s);
 }
 
-bool order_supported(const Geom &g, int order) {
-    return order == 0 || (order == 1 && g.vh % 64 == 0 && (g.lxh * g.L[1]) % 64 == 0);
+bool order_supported(const Geom &g, int order, int block) {
+    const int kind = order & 0xff;
+    if (order < 0) return false;
+    if (kind == 0) return order == 0;
+    if (g.vh % 64 || (g.lxh * g.L[1]) % 64) return false;
+    if (kind == 1) return order == 1;
+    if (kind != 2 || (order >> 24)) return false;
+    // whole tiles per column row block, whole blocks, and a grid of whole
+    // eighths (the XCD remap is a permutation only then)
+    const int by = (order >> 8) & 0xff, bz = (order >> 16) & 0xff;
+    if (by < 1 || bz < 1 || g.L[1] % by || g.L[2] % bz || (g.lxh * by) % 64) return false;
+    if (block < 64 || g.vh % block) return false;
+    return (g.vh / block) % 8 == 0;
 }
 
 int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s) {
@@ -239,7 +297,7 @@ int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s) {
         set_error("dslash: block size must be 64, 128 or 256");
         return HISQ_ERR_INVALID;
     }
-    if (!order_supported(g, a.order)) {
+    if (!order_supported(g, a.order, a.block)) {
         set_error("dslash: traversal order not supported for this lattice");
         return HISQ_ERR_INVALID;
     }

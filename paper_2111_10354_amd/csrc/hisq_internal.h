@@ -443,11 +443,12 @@ struct DslashLaunch {
     int fmt_links, fmt_in, fmt_out;
     int tile;
     int block;
-    int order;  // tile processing order (0 memory order, 1 t-fastest planes)
+    int order;  // tile processing order: 0 memory order, 1 t-fastest planes,
+                // 2 | BY << 8 | BZ << 16 XCD bricks (dslash.hip)
     int compressed;  // links in the compressed layout
 };
 int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s);
-bool order_supported(const Geom &g, int order);
+bool order_supported(const Geom &g, int order, int block);
 int dslash_grid_blocks(const Geom &g, int block);
 
 }  // namespace hisq
