@@ -99,6 +99,7 @@ def main():
                                                                   "gfx950.jsonl"),
                     help="autotuner cache (JSON lines); shapes found there are used without timing")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 48^3x12 multi-RHS sweep")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 48^3x12 batched and multi-shift solves")
     ap.add_argument("--fields-cache", type=str, default=None,
                     help="directory to save / reuse the generated link fields (profiling re-runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -271,6 +272,11 @@ def main():
     if not (args.quick or args.no_cg):
         cg = run_cg(hisq, torch)
 
+    # ---- batched and multi-shift solves on the 48^3 x 12 workload
+    c3 = None
+    if not (args.quick or args.no_cg or args.no_c3):
+        c3 = run_c3_solvers(hisq, torch, tune)
+
     # ---- network preconditioner on the 32^3 x 8, m = 0.005 workload
     nnres = None
     if not (args.quick or args.no_nn):
@@ -301,6 +307,7 @@ def main():
         "parity_sample_rel_l2": perr,
         "variants": variants,
         "cg": cg,
+        "c3_solvers": c3,
         "nn_fcg": nnres,
     }
     result["config"]["launch_shape"] = {"rhs_tile": shape[0], "block": shape[1], "tile_order": shape[2]}
@@ -371,6 +378,75 @@ def run_cg(hisq, torch):
     best = min(("mixed_fp32", "mixed_fp16s"), key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
     out["chosen"] = best
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
+    g.close()
+    return out
+
+
+def run_c3_solvers(hisq, torch, tune):
+    """48^3 x 12, m = 0.005: one RHS by plain FP64 CG and by mixed FP32 CG, all
+    16 RHS batched through the multi-RHS Dslash (mixed FP32, FP64 reliable
+    updates), and the 12-shift ladder sigma_k = 10^(-4 + 4k/11) by multi-shift
+    CG; every solve to the 1e-10 FP64 true residual."""
+    import synth
+    c = synth.CONFIGS["c3"]
+    dims, mass, n, ns = c["dims"], c["mass"], c["nrhs"], c["nshift"]
+    vh = synth.volume(dims) // 2
+    log(f"C3 solves {dims} m={mass}: generating fields")
+    F, L = synth.hisq_links(dims, synth.CFG_IDS["c3"], c["eps"])
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32"))
+    del F, L
+    for p in ("fp64", "fp32"):
+        for k in (1, n, ns):
+            hisq.autotune(g, p, k, tune)
+    srcs = synth.gaussian_source(dims, synth.CFG_IDS["c3"], n, parity=0)
+    b = torch.from_numpy(np.concatenate([encode(cb_gather(dims, s_, 0)[0], "fp64") for s_ in srcs])).cuda()
+    sb = hisq.spinor_bytes("fp64", vh)
+    out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, tol 1e-10 (FP64 true residual)",
+           "long_links_compressed": g.compressed}
+
+    def timed(fn, warm):
+        warm()
+        torch.cuda.synchronize()
+        t1 = time.time()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.time() - t1
+
+    def summary(rc, st, wall, k):
+        return {"status": rc, "seconds": round(wall, 4), "seconds_per_rhs": round(wall / k, 4),
+                "iterations_max": max(v["iterations"] for v in st),
+                "true_residual_max": max(v["true_residual"] for v in st)}
+
+    b0 = b[:sb]
+    for name, sloppy in (("plain_fp64_1rhs", "fp64"), ("mixed_fp32_1rhs", "fp32")):
+        x = torch.zeros_like(b0)
+        (rc, st), wall = timed(lambda: hisq.cg_solve(g, mass, 1, b0, x, hisq.solver_params(sloppy_prec=sloppy)),
+                               lambda: hisq.cg_solve(g, mass, 1, b0, torch.zeros_like(b0),
+                                                     hisq.solver_params(sloppy_prec=sloppy, max_iter=50)))
+        out[name] = summary(rc, st, wall, 1)
+        log(f"C3 {name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
+    x = torch.zeros_like(b)
+    (rc, st), wall = timed(lambda: hisq.cg_solve(g, mass, n, b, x, hisq.solver_params(sloppy_prec="fp32")),
+                           lambda: hisq.cg_solve(g, mass, n, b, torch.zeros_like(b),
+                                                 hisq.solver_params(sloppy_prec="fp32", max_iter=50)))
+    out[f"batched_mixed_fp32_{n}rhs"] = summary(rc, st, wall, n)
+    log(f"C3 batched mixed FP32, {n} RHS: {wall:.3f} s ({wall / n:.3f} s per RHS), "
+        f"max {out[f'batched_mixed_fp32_{n}rhs']['iterations_max']} it, "
+        f"worst true res {out[f'batched_mixed_fp32_{n}rhs']['true_residual_max']:.2e}")
+    shifts = [float(v) for v in synth.shifted_ladder(ns)]
+    xs = torch.zeros(ns * sb, dtype=torch.uint8, device="cuda")
+    (rc, st), wall = timed(lambda: hisq.multishift_cg(g, mass, shifts, b0, xs),
+                           lambda: hisq.multishift_cg(g, mass, shifts, b0, torch.zeros_like(xs),
+                                                      hisq.solver_params(max_iter=50)))
+    ms = summary(rc, st, wall, ns)
+    ms["shifts"] = shifts
+    ms["iterations_base"] = st[int(np.argmin(shifts))]["iterations"]
+    out[f"multishift_fp64_{ns}shifts"] = ms
+    log(f"C3 multi-shift, {ns} shifts: {wall:.3f} s, base {ms['iterations_base']} it, "
+        f"worst true res {ms['true_residual_max']:.2e}")
+    p1 = out["plain_fp64_1rhs"]["seconds"]
+    out["speedup_batched_per_rhs_vs_plain"] = round(p1 / out[f"batched_mixed_fp32_{n}rhs"]["seconds_per_rhs"], 3)
+    out["speedup_multishift_per_shift_vs_plain"] = round(p1 / ms["seconds_per_rhs"], 3)
     g.close()
     return out
 

@@ -213,7 +213,8 @@ void hisq_solver_params_default(hisq_solver_params *p);
  * With p->precond set, each right-hand side is solved in turn by flexible CG
  * (Notay, SIAM J. Sci. Comput. 22 (2000), FCG(1): the learned preconditioner
  * beside the paper's solver family, which is an extension of it) with z = N(r) in FP32, complex step sizes and FP64 reliable updates every
- * ru_period iterations, each restarting the direction from N(r); the network
+ * ru_period iterations, after which the iteration continues from the
+ * recomputed residual with the current search direction; the network
  * must belong to g and the handle needs FP64 and FP32 links plus thin links.
  * A breakdown, or three reliable updates in a row that fail to halve the true
  * residual, hands the solve to plain FP64 CG from the current x when
