@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import fields, hisq, make_gauge, to_device, to_host
+from gpu_util import fields, force_shape, hisq, make_gauge, to_device, to_host
 from layout import decode, encode, from_cb, rel_l2, spinor_nbytes, to_cb
 
 pytestmark = pytest.mark.gpu
@@ -52,19 +52,6 @@ def test_autotune_keeps_output_and_caches(tmp_path, cuda_device, prec, nrhs):
     g2.close()
 
 
-def _force_shape(g, prec, nrhs, epi, shape, path):
-    """Install a launch shape through a one-line cache file for the key the
-    autotuner itself writes for this handle."""
-    probe = path.with_suffix(".probe")
-    hisq().autotune(g, prec, nrhs, str(probe))
-    keys = [json.loads(line)["key"] for line in probe.read_text().splitlines()]
-    key = [k for k in keys if k.endswith(f"|n{nrhs}|e{epi}") or f"|n{nrhs}|e{epi}|" in k][0]
-    tile, block, order = shape
-    path.write_text(f'{{"key": "{key}", "tile": {tile}, "block": {block}, "order": {order}, "ms": 0.000000}}\n')
-    hisq().autotune(g, prec, nrhs, str(path))
-    return hisq().dslash_shape(g, prec, nrhs, epi)
-
-
 BRICK = [2 | 8 << 8 | 16 << 16, 2 | 16 << 8 | 8 << 16, 2 | 8 << 8 | 4 << 16]
 
 
@@ -83,13 +70,13 @@ def test_brick_orders_match_memory_order(tmp_path, cuda_device, prec, nrhs, tile
     inp = to_device(raw)
     nb = spinor_nbytes(prec, vh)
     ref = torch.empty(nb * nrhs, dtype=torch.uint8, device="cuda")
-    assert _force_shape(g, prec, nrhs, 0, (1, 256, 0), tmp_path / "m.jsonl") == (1, 256, 0)
+    assert force_shape(g, prec, nrhs, 0, (1, 256, 0), tmp_path / "m.jsonl") == (1, 256, 0)
     hisq().dslash_multi_rhs(g, 0, prec, nrhs, inp, ref)
     ref_h = to_host(ref)
     for i, order in enumerate(BRICK):
         for block in (64, 256):
             shape = (tile, block, order)
-            assert _force_shape(g, prec, nrhs, 0, shape, tmp_path / f"b{i}{block}.jsonl") == shape
+            assert force_shape(g, prec, nrhs, 0, shape, tmp_path / f"b{i}{block}.jsonl") == shape
             out = torch.full_like(ref, 0xAB)
             hisq().dslash_multi_rhs(g, 0, prec, nrhs, inp, out)
             assert np.array_equal(to_host(out), ref_h), shape
@@ -112,8 +99,8 @@ def test_brick_order_in_solver(tmp_path, cuda_device):
     g = make_gauge(dims, F, L)
     for prec, tile in (("fp32", 2), ("fp64", 2)):
         shape = (tile, 128, BRICK[0])
-        assert _force_shape(g, prec, 2, 1, shape, tmp_path / f"s{prec}.jsonl") == shape
-        assert _force_shape(g, prec, 2, 0, shape, tmp_path / f"s0{prec}.jsonl") == shape
+        assert force_shape(g, prec, 2, 1, shape, tmp_path / f"s{prec}.jsonl") == shape
+        assert force_shape(g, prec, 2, 0, shape, tmp_path / f"s0{prec}.jsonl") == shape
     mass = 0.1
     srcs = synth.gaussian_source(dims, 1, 2, parity=0, index0=81)
     vh = synth.volume(dims) // 2

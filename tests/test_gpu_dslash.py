@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import fields, flush, hisq, make_gauge, to_device, to_host
+from gpu_util import fields, flush, force_shape, hisq, make_gauge, to_device, to_host
 from layout import decode, encode, from_cb, rel_l2, spinor_nbytes, to_cb
 
 pytestmark = pytest.mark.gpu
@@ -182,6 +182,53 @@ def test_multi_rhs_shifted_epilogue(gauges, prec):
         yq = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 0)
         want = to_cb(dims, oracle.normal_op(dims, F, L, mass, yq, sigma=sig[i]), 0)
         assert rel_l2(decode(got[i], vh, prec), want) <= tol
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_ragged_rhs_tiles(tmp_path, cuda_device, prec, full):
+    """9 RHS in tiles of 2, 4 and 8 (the last tile ragged: its missing RHS
+    repeat the last one and are never stored), plain and with the (A + sigma_i)
+    epilogue: every tile writes exactly what one RHS per thread writes, and
+    nothing beyond the 9 outputs."""
+    import torch
+    dims = (10, 6, 4, 8)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L, full_links=full)
+    vh = synth.volume(dims) // 2
+    n = 9
+    mass = 0.1
+    diag = [4 * mass * mass + s for s in (0.0, 1e-3, 0.1, 1.0, 3.0, 0.02, 0.5, 2.0, 1e-4)]
+    srcs = synth.gaussian_source(dims, 97, n, parity=1, index0=30)
+    raw = np.concatenate([encode(to_cb(dims, s, 1), prec) for s in srcs])
+    ys = synth.gaussian_source(dims, 97, n, parity=0, index0=40)
+    yraw = np.concatenate([encode(to_cb(dims, y, 0), prec) for y in ys])
+    inp, y = to_device(raw), to_device(yraw)
+    nb = spinor_nbytes(prec, vh)
+    guard = 4 * nb
+
+    def run(shape):
+        assert force_shape(g, prec, n, 0, shape, tmp_path / f"p{shape[0]}.jsonl") == shape
+        assert force_shape(g, prec, n, 1, shape, tmp_path / f"e{shape[0]}.jsonl") == shape
+        out = torch.full((nb * n + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+        epi = torch.full((nb * n + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+        hisq().dslash_multi_rhs(g, 0, prec, n, inp, out)
+        hisq().dslash_multi_rhs(g, 0, prec, n, inp, epi, diag=diag, y=y)
+        o, e = to_host(out), to_host(epi)
+        assert np.all(o[nb * n:] == 0x5A) and np.all(e[nb * n:] == 0x5A)
+        return o[:nb * n], e[:nb * n]
+
+    ref, ref_e = run((1, 64, 0))
+    tiles = (2, 4) if prec == "fp64" else (2, 4, 8)
+    for tile in tiles:
+        got, got_e = run((tile, 128, 0))
+        assert np.array_equal(got, ref), tile
+        assert np.array_equal(got_e, ref_e), tile
+    for i in range(n):
+        chi_q = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 1)
+        want = to_cb(dims, oracle.dslash(dims, F, L, chi_q, 0), 0)
+        assert rel_l2(decode(ref[i * nb:(i + 1) * nb], vh, prec), want) <= TOL[prec]
+    g.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
