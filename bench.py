@@ -123,6 +123,8 @@ def main():
 
     import synth  # input generator only
     if args.c5_solve:
+        # minutes-long solves: the library reports progress every 2000 iterations
+        os.environ.setdefault("HISQ_SOLVER_TRACE", "1")
         print(json.dumps(run_c5_solve(with_fp16s=args.c5_fp16s)), flush=True)
         return
     dims = tuple(int(v) for v in args.dims.split(","))
