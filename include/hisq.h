@@ -240,6 +240,46 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
                        hisq_solver_stats *st, void *stream);
 
 /*
+ * Rational functions of A, the solver-side part of rational hybrid Monte
+ * Carlo (the paper's RHMC for 2+1 flavours and its multiple-shift CG, Sec. 2;
+ * most of the RHMC time goes into these CG solves, Sec. 3): with a rational
+ * approximation in partial fractions,
+ *     out = alpha0 b + sum_k alpha[k] (A + shift[k])^(-1) b
+ * computed by one multi-shift CG (hisq_multishift_cg, each shift to p->tol on
+ * its FP64 true residual) and one FP64 linear combination.
+ *   alpha, shift host double[nterm] (0 <= nterm <= 256; nterm = 0 gives
+ *                alpha0 b), every shift + 4 m^2 > 0
+ *   b, out       device FP64 spinors [3][Vh] (even sites), not overlapping
+ *   st           host array of nterm stats (or NULL)
+ * Needs FP64 links in the handle.  Returns the worst multi-shift status.
+ */
+int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, const double *alpha,
+                        const double *shift, const double *b, double *out,
+                        const hisq_solver_params *p, hisq_solver_stats *st, void *stream);
+
+/*
+ * Zolotarev's optimal rational approximation of x^(-1/2) on [lmin, lmax]
+ * (minimax relative error; E. I. Zolotarev 1877, in the partial-fraction form
+ * used for rooted staggered pseudofermions): on return
+ *     x^(-1/2) ~ *alpha0 + sum_k alpha[k] / (x + shift[k]),  k < npole,
+ * with 0 < shift[0] < ... < shift[npole-1], every alpha[k] > 0, and *delta
+ * (may be NULL) the largest relative error over the interval; the error
+ * equioscillates 2 npole + 2 times.  Host only (no GPU).
+ *   0 < lmin < lmax, lmax / lmin <= 1e14, 1 <= npole <= 64
+ */
+int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0, double *alpha,
+                            double *shift, double *delta);
+
+/*
+ * Spectrum bounds of A for a rational approximation: *lmin = 4 m^2 (a lower
+ * bound, since (D^+ D)_ee >= 0) and *lmax = the Rayleigh quotient of A after
+ * `iters` FP64 power iterations from a fixed pseudo-random vector, an
+ * estimate from below of the largest eigenvalue (enlarge it by a margin
+ * before use).  Synchronous; needs FP64 links.
+ */
+int hisq_spectral_bounds(hisq_gauge_t g, double mass, int iters, double *lmin, double *lmax, void *stream);
+
+/*
  * Gauge-covariant preconditioner network, z = N(r): a stack of linear layers
  * psi'_a(x) = sum_b [ W0_ab psi_b(x) + sum_mu ( Wf_mu,ab U_mu(x) psi_b(x+mu)
  *                                            + Wb_mu,ab U_mu(x-mu)^+ psi_b(x-mu) ) ]

@@ -14,7 +14,10 @@ Parts:
   closed-form spectrum;
 * ``gauge``: gauge transformations and the plaquette (pins of the covariance
   tests);
-* ``nn``: the gauge-covariant preconditioner network and its gradient.
+* ``nn``: the gauge-covariant preconditioner network and its gradient;
+* ``rational``: rational functions of the normal operator (partial-fraction
+  sums by independent CGs, exact dense powers, Zolotarev's approximation of
+  x^(-1/2)).
 """
 
 from .core import (  # noqa: F401

@@ -1,0 +1,105 @@
+"""Rational functions of the even-site normal operator A (test infrastructure).
+
+What a rational-approximation solver must return, written from definitions:
+* ``rational_apply``: alpha_0 b + sum_k alpha_k (A + sigma_k)^-1 b with every
+  shifted system solved by its own plain FP64 CG (the definition of the
+  partial-fraction sum; the multi-shift recurrence is not used);
+* ``dense_power``: A^p b exactly, from the eigen-decomposition of the dense A
+  on a tiny lattice;
+* ``zolotarev_inv_sqrt``: Zolotarev's optimal rational approximation of
+  x^(-1/2) on [lmin, lmax] (minimax relative error), built from the Jacobi
+  elliptic functions of scipy: with k'^2 = 1 - lmin/lmax and K' = K(k'),
+  c_l = sn^2 / cn^2 (l K' / (2n + 1)), l = 1..2n, and
+  r(x) = D prod_l (x + c_{2l}) / (x + c_{2l-1}) on [1, lmax/lmin], D centring
+  the relative error; then partial fractions and rescaling to [lmin, lmax];
+* ``relative_error_extrema``: the local extrema of x^(1/2) r(x) - 1 on a fine
+  logarithmic grid, for the alternation test (a best approximation of type
+  (n, n) has 2n + 2 alternating extrema of equal size - Chebyshev).
+Shares no code with the HIP library.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .core import cg
+from .dense import dense_normal_op, parity_index
+
+
+def rational_apply(dims, fat, lng, mass, alpha0, alphas, shifts, b, tol=1e-12):
+    """alpha0 b + sum_k alphas[k] (A + shifts[k])^-1 b; b full-lattice (V, 3) on even sites."""
+    out = alpha0 * np.asarray(b, dtype=np.complex128)
+    for a, s in zip(alphas, shifts):
+        x, st, _, _ = cg(dims, fat, lng, mass, b, tol=tol, sigma=float(s))
+        if st != 0:
+            raise RuntimeError(f"oracle CG for shift {s} did not converge")
+        out = out + a * x
+    return out
+
+
+def dense_power(dims, fat, lng, mass, b, p):
+    """A^p b (full-lattice (V, 3) in and out, even sites) and A's extreme eigenvalues."""
+    A = dense_normal_op(dims, fat, lng, mass)
+    w, Q = np.linalg.eigh(A)
+    e = parity_index(dims, 0)
+    be = np.asarray(b, dtype=np.complex128).ravel()[e]
+    ye = Q @ (w ** p * (Q.conj().T @ be))
+    out = np.zeros(int(np.prod(dims)) * 3, dtype=np.complex128)
+    out[e] = ye
+    return out.reshape(-1, 3), float(w[0]), float(w[-1])
+
+
+def _product(x, c, n):
+    r = np.ones_like(x)
+    for l in range(n):
+        r = r * (x + c[2 * l + 1]) / (x + c[2 * l])
+    return r
+
+
+def zolotarev_inv_sqrt(lmin, lmax, n):
+    """(alpha0, alphas, shifts, delta) with x^(-1/2) ~ alpha0 + sum alphas / (x + shifts)."""
+    from scipy.special import ellipj, ellipk
+    b = lmax / lmin
+    m = 1.0 - 1.0 / b
+    K = ellipk(m)
+    sn, cn, _, _ = ellipj(np.arange(1, 2 * n + 1) * K / (2 * n + 1), m)
+    c = sn ** 2 / cn ** 2
+    x = np.exp(np.linspace(0.0, np.log(b), 400 * n + 401))
+    f = np.sqrt(x) * _product(x, c, n)
+    # refine every interior extremum by a parabola through the grid triple
+    lo, hi = [f[0], f[-1]], [f[0], f[-1]]
+    i = np.arange(1, len(f) - 1)
+    for k in i[((f[i] - f[i - 1]) * (f[i + 1] - f[i])) <= 0]:
+        u = np.log(x[k - 1:k + 2])
+        cf = np.polyfit(u, f[k - 1:k + 2], 2)
+        if cf[0] != 0:
+            uv = -cf[1] / (2 * cf[0])
+            if u[0] <= uv <= u[2]:
+                xv = np.exp(uv)
+                fv = float(np.sqrt(xv) * _product(np.array([xv]), c, n)[0])
+                lo.append(fv)
+                hi.append(fv)
+        lo.append(f[k])
+        hi.append(f[k])
+    fmin, fmax = min(lo), max(hi)
+    D = 2.0 / (fmin + fmax)
+    delta = (fmax - fmin) / (fmax + fmin)
+    p = c[0::2]
+    num = c[1::2]
+    res = np.empty(n)
+    for l in range(n):
+        v = D * np.prod(num - p[l])
+        others = np.delete(p, l)
+        res[l] = v / np.prod(others - p[l])
+    s = np.sqrt(lmin)
+    return D / s, res * s, p * lmin, float(delta)
+
+
+def relative_error_extrema(alpha0, alphas, shifts, lmin, lmax, npts=200001):
+    """Values of x^(1/2) r(x) - 1 at its local extrema on [lmin, lmax] (ends included)."""
+    x = np.exp(np.linspace(np.log(lmin), np.log(lmax), npts))
+    r = alpha0 + sum(a / (x + s) for a, s in zip(alphas, shifts))
+    e = np.sqrt(x) * r - 1.0
+    d = np.diff(e)
+    k = np.where(np.sign(d[1:]) != np.sign(d[:-1]))[0] + 1
+    return np.concatenate([[e[0]], e[k], [e[-1]]])

@@ -294,6 +294,53 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }
 
+int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0, double *alpha, double *shift,
+                            double *delta) {
+    if (!(lmin > 0.0) || !std::isfinite(lmin) || !std::isfinite(lmax) || !(lmax > lmin))
+        return fail(HISQ_ERR_INVALID, "need 0 < lmin < lmax, both finite");
+    if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
+    if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
+    if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
+    return zolotarev_inv_sqrt(lmin, lmax, npole, alpha0, alpha, shift, delta);
+}
+
+int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, const double *alpha,
+                        const double *shift, const double *b, double *out, const hisq_solver_params *p,
+                        hisq_solver_stats *st, void *stream) {
+    TraceRange tr_("hisq_rational_apply");
+    int rc = check_handle(g);
+    if (rc) return rc;
+    hisq_solver_params prm;
+    if (p) prm = *p;
+    else hisq_solver_params_default(&prm);
+    if ((rc = check_params(prm))) return rc;
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
+    if (prm.precond) return fail(HISQ_ERR_UNSUPPORTED, "rational apply takes no preconditioner");
+    if (nterm < 0 || nterm > 256) return fail(HISQ_ERR_INVALID, "0 <= nterm <= 256");
+    if (nterm > 0 && (!alpha || !shift)) return fail(HISQ_ERR_INVALID, "alpha and shift are required");
+    if (!std::isfinite(alpha0)) return fail(HISQ_ERR_INVALID, "alpha0 must be finite");
+    for (int k = 0; k < nterm; ++k)
+        if (!std::isfinite(alpha[k]) || !std::isfinite(shift[k]) || !(shift[k] + 4.0 * mass * mass > 0.0))
+            return fail(HISQ_ERR_INVALID, "every alpha and shift must be finite with shift + 4 m^2 > 0");
+    if (!b || !out) return fail(HISQ_ERR_INVALID, "b and out are required");
+    if (b == out) return fail(HISQ_ERR_INVALID, "b and out must not overlap");
+    if ((rc = check_spinors(b, out))) return rc;
+    if (!g->links[F64][0].p) return fail(HISQ_ERR_UNSUPPORTED, "the handle lacks packed FP64 links");
+    std::lock_guard<std::mutex> lk(g->mu);
+    return rational_apply(g, mass, alpha0, nterm, alpha, shift, b, out, prm, st, (hipStream_t)stream);
+}
+
+int hisq_spectral_bounds(hisq_gauge_t g, double mass, int iters, double *lmin, double *lmax, void *stream) {
+    TraceRange tr_("hisq_spectral_bounds");
+    int rc = check_handle(g);
+    if (rc) return rc;
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
+    if (iters < 1 || iters > 100000) return fail(HISQ_ERR_INVALID, "1 <= iters <= 100000");
+    if (!lmin || !lmax) return fail(HISQ_ERR_INVALID, "lmin and lmax are required");
+    std::lock_guard<std::mutex> lk(g->mu);
+    return spectral_bounds(g, mass, iters, lmin, lmax, (hipStream_t)stream);
+}
+
 int hisq_autotune(hisq_gauge_t g, int prec, int nrhs, const char *cache_path, void *stream) {
     TraceRange tr_("hisq_autotune");
     int rc = check_handle(g);

@@ -173,4 +173,16 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
 int multishift_solve(hisq_gauge_s *g, double mass, int nshift, const double *shifts, const double *b,
                      double *x, const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);
 
+// Zolotarev's minimax relative approximation of x^(-1/2) on [lmin, lmax] in
+// partial fractions alpha0 + sum_k alpha[k] / (x + shift[k]); delta = its
+// maximal relative error.  Host only.
+int zolotarev_inv_sqrt(double lmin, double lmax, int n, double *alpha0, double *alpha, double *shift,
+                       double *delta);
+// out = alpha0 b + sum_k alpha[k] (A + shift[k])^(-1) b by one multi-shift CG.
+int rational_apply(hisq_gauge_s *g, double mass, double alpha0, int n, const double *alpha, const double *shift,
+                   const double *b, double *out, const hisq_solver_params &prm, hisq_solver_stats *st,
+                   hipStream_t s);
+// lmin = 4 m^2 (a bound); lmax = Rayleigh quotient after `iters` power iterations.
+int spectral_bounds(hisq_gauge_s *g, double mass, int iters, double *lmin, double *lmax, hipStream_t s);
+
 }  // namespace hisq

@@ -77,6 +77,10 @@ def _load():
         "hisq_nn_train_step": (C.c_int, [vp, C.c_int, vp, vp, C.c_double, dp, vp]),
         "hisq_dslash_shape": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]),
         "hisq_gauge_links_compressed": (C.c_int, [vp]),
+        "hisq_rational_apply": (C.c_int, [vp, C.c_double, C.c_double, C.c_int, dp, dp, vp, vp,
+                                          C.POINTER(SolverParams), C.POINTER(SolverStats), vp]),
+        "hisq_zolotarev_inv_sqrt": (C.c_int, [C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
+        "hisq_spectral_bounds": (C.c_int, [vp, C.c_double, C.c_int, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -93,7 +97,8 @@ EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_c
            "hisq_solver_params_default", "hisq_cg_solve", "hisq_multishift_cg", "hisq_precond_apply",
            "hisq_autotune", "hisq_dslash_shape", "hisq_gauge_set_thin", "hisq_nn_create", "hisq_nn_destroy",
            "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
-           "hisq_nn_train_step", "hisq_gauge_links_compressed")
+           "hisq_nn_train_step", "hisq_gauge_links_compressed", "hisq_rational_apply",
+           "hisq_zolotarev_inv_sqrt", "hisq_spectral_bounds")
 
 LINKS_FULL = 1 << 8  # hisq_gauge_create: store every link whole
 
@@ -233,6 +238,37 @@ def multishift_cg(g: Gauge, mass: float, shifts, b, x, params: SolverParams | No
                                 C.byref(params) if params is not None else None, st, _stream(stream))
     _check(rc, allow_soft=True)
     return rc, [s.as_dict() for s in st]
+
+
+def rational_apply(g: Gauge, mass: float, alpha0: float, alphas, shifts, b, out,
+                   params: SolverParams | None = None, stream=None):
+    """out = alpha0 b + sum_k alphas[k] (A + shifts[k])^-1 b; returns (status, [stats per term])."""
+    n = len(shifts)
+    if len(alphas) != n:
+        raise ValueError("alphas and shifts differ in length")
+    al = (C.c_double * max(n, 1))(*[float(v) for v in alphas])
+    sh = (C.c_double * max(n, 1))(*[float(v) for v in shifts])
+    st = (SolverStats * max(n, 1))()
+    rc = LIB.hisq_rational_apply(g.handle, float(mass), float(alpha0), n, al, sh, _ptr(b), _ptr(out),
+                                 C.byref(params) if params is not None else None, st, _stream(stream))
+    _check(rc, allow_soft=True)
+    return rc, [s.as_dict() for s in st[:n]]
+
+
+def zolotarev_inv_sqrt(lmin: float, lmax: float, npole: int):
+    """(alpha0, alphas, shifts, delta): x^(-1/2) ~ alpha0 + sum_k alphas[k] / (x + shifts[k]) on
+    [lmin, lmax] with maximal relative error delta (host only)."""
+    a0, dl = C.c_double(0.0), C.c_double(0.0)
+    al, sh = (C.c_double * npole)(), (C.c_double * npole)()
+    _check(LIB.hisq_zolotarev_inv_sqrt(float(lmin), float(lmax), int(npole), C.byref(a0), al, sh, C.byref(dl)))
+    return a0.value, list(al), list(sh), dl.value
+
+
+def spectral_bounds(g: Gauge, mass: float, iters: int = 100, stream=None):
+    """(4 m^2, Rayleigh-quotient estimate of the largest eigenvalue of A)."""
+    lo, hi = C.c_double(0.0), C.c_double(0.0)
+    _check(LIB.hisq_spectral_bounds(g.handle, float(mass), int(iters), C.byref(lo), C.byref(hi), _stream(stream)))
+    return lo.value, hi.value
 
 
 def autotune(g: Gauge, prec, nrhs: int, cache_path: str | None = None, stream=None):

@@ -1,0 +1,102 @@
+"""GPU rational functions of A (hisq_rational_apply, hisq_spectral_bounds)
+against the oracle: the exact dense A^(-1/2) b on 4^4 within the Zolotarev
+error bound, and the oracle's partial-fraction sum (independent CGs per pole)
+on larger lattices within the solver tolerance.
+
+Tolerance of the partial-fraction sum: every shifted solve stops at a true
+relative residual <= 1e-10, so |x_k - x_k*| <= 1e-10 |b| / (lmin + sigma_k);
+summed with the positive residues, the result differs from the exact sum by
+at most 1e-10 |b| sum_k alpha_k / (lmin + sigma_k) <= 1e-10 |b| r(lmin), i.e.
+about 1e-10 (1 + delta) |b| / sqrt(lmin) - well under 1e-8 relative here.
+"""
+
+import numpy as np
+import pytest
+
+import oracle.rational as R
+import synth
+from gpu_util import fields, flush, hisq, make_gauge, to_device, to_host
+from layout import decode, encode, from_cb, to_cb
+
+pytestmark = pytest.mark.gpu
+
+
+def run(g, dims, mass, a0, al, sh, b, **kw):
+    import torch
+    vh = synth.volume(dims) // 2
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    out = torch.full_like(bd, 0x77)
+    rc, st = hisq().rational_apply(g, mass, a0, al, sh, bd, out, hisq().solver_params(**kw))
+    return rc, st, from_cb(dims, decode(to_host(out), vh, "fp64"), 0)
+
+
+def test_inverse_sqrt_matches_dense(cuda_device):
+    dims = (4, 4, 4, 4)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L)
+    mass = 0.1
+    b = synth.gaussian_source(dims, 11, 1, parity=0)[0]
+    exact, lo, hi = R.dense_power(dims, F, L, mass, b, -0.5)
+    for npole in (4, 10):
+        a0, al, sh, delta = hisq().zolotarev_inv_sqrt(lo, hi, npole)
+        flush(f"rational 4^4 npole={npole} delta={delta:.2e}")
+        rc, st, got = run(g, dims, mass, a0, al, sh, b)
+        assert rc == 0, st
+        err = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+        assert err <= delta * (1 + 1e-6) + 1e-8, (npole, err, delta)
+        # pseudofermion action b^+ A^(-1/2) b
+        s_gpu = np.vdot(b, got).real
+        s_exact = np.vdot(b, exact).real
+        assert abs(s_gpu / s_exact - 1) <= delta + 1e-8
+    g.close()
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
+def test_partial_fractions_match_oracle(cuda_device, full):
+    dims = (8, 8, 8, 8)
+    F, L = fields(dims, cfg_id=0, eps=0.3)
+    g = make_gauge(dims, F, L, full_links=full)
+    mass = 0.05
+    lo, hi = hisq().spectral_bounds(g, mass, 200)
+    a0, al, sh, delta = hisq().zolotarev_inv_sqrt(lo, 1.05 * hi, 12)
+    b = synth.gaussian_source(dims, 12, 1, parity=0)[0]
+    flush(f"rational 8^4 bounds [{lo:.3e}, {hi:.3e}] delta={delta:.2e}")
+    rc, st, got = run(g, dims, mass, a0, al, sh, b)
+    assert rc == 0, st
+    assert all(s["true_residual"] <= 1e-10 for s in st)
+    want = R.rational_apply(dims, F, L, mass, a0, al, sh, b, tol=1e-12)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-8
+    g.close()
+
+
+def test_spectral_bounds_against_dense(cuda_device):
+    dims = (4, 4, 4, 4)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L)
+    mass = 0.1
+    _, lo, hi = R.dense_power(dims, F, L, mass, synth.gaussian_source(dims, 1, 1, parity=0)[0], 1.0)
+    blo, bhi = hisq().spectral_bounds(g, mass, 300)
+    assert blo == pytest.approx(4 * mass * mass, rel=1e-15) and blo <= lo * (1 + 1e-12)
+    # a Rayleigh quotient never exceeds the top eigenvalue; 300 steps get close
+    assert 0.9 * hi <= bhi <= hi * (1 + 1e-12), (bhi, hi)
+    g.close()
+
+
+def test_degenerate_and_invalid(cuda_device):
+    import torch
+    dims = (4, 4, 4, 4)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L)
+    b = synth.gaussian_source(dims, 13, 1, parity=0)[0]
+    # no poles: out = alpha0 b exactly
+    rc, st, got = run(g, dims, 0.1, 2.5, [], [], b)
+    assert rc == 0 and np.array_equal(got, 2.5 * b)   # b vanishes on odd sites
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    out = torch.empty_like(bd)
+    with pytest.raises(hisq().HisqError):   # shift below -4 m^2
+        hisq().rational_apply(g, 0.1, 0.0, [1.0], [-0.05], bd, out)
+    with pytest.raises(hisq().HisqError):   # in place
+        hisq().rational_apply(g, 0.1, 0.0, [1.0], [0.1], bd, bd)
+    with pytest.raises(hisq().HisqError):
+        hisq().spectral_bounds(g, -0.1, 10)
+    g.close()

@@ -1,0 +1,95 @@
+"""Rational approximation of A^(-1/2) (the rooted-staggered pseudofermion
+operator of RHMC): pins of the oracle's Zolotarev construction and of its
+partial-fraction application, and the library's host-side coefficients
+against the oracle.  No GPU.
+
+Pins that do not reuse the construction being tested:
+* Chebyshev alternation: a best relative approximation of type (n, n) has
+  2n + 2 alternating extrema of equal size, and any wrong coefficient (a
+  misplaced pole, the wrong elliptic argument, a dropped factor) breaks it;
+* the exact dense power A^(-1/2) b on a 4^4 lattice, which the partial-fraction
+  sum must reproduce within the approximation's own error bound delta
+  (|r(l) - l^(-1/2)| <= delta l^(-1/2) for every eigenvalue l in the interval);
+* one term with alpha = 1, sigma = 0 and alpha0 = 0 is A^(-1) b.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rational as R
+
+CASES = [(1, 10.0), (4, 1e4), (8, 1e6), (12, 1e7)]
+
+
+@pytest.mark.parametrize("n,ratio", CASES)
+def test_oracle_zolotarev_equioscillates(n, ratio):
+    lmin = 3e-3
+    a0, al, sh, delta = R.zolotarev_inv_sqrt(lmin, lmin * ratio, n)
+    ex = R.relative_error_extrema(a0, al, sh, lmin, lmin * ratio)
+    assert len(ex) == 2 * n + 2
+    assert np.all(np.sign(ex[1:]) != np.sign(ex[:-1]))
+    mags = np.abs(ex)
+    assert mags.max() / mags.min() - 1 < 1e-5
+    assert abs(mags.max() / delta - 1) < 1e-5
+    # poles on the negative axis, positive residues: every shifted system is HPD
+    assert np.all(np.array(sh) > 0) and np.all(np.diff(sh) > 0) and np.all(np.array(al) > 0) and a0 > 0
+
+
+def test_oracle_zolotarev_error_falls_with_poles():
+    d = [R.zolotarev_inv_sqrt(1e-3, 10.0, n)[3] for n in (2, 4, 6, 8, 10)]
+    assert all(b < a for a, b in zip(d, d[1:]))
+    # and the bound holds off the grid the construction used
+    a0, al, sh, delta = R.zolotarev_inv_sqrt(1e-3, 10.0, 6)
+    x = np.exp(np.random.default_rng(0).uniform(np.log(1e-3), np.log(10.0), 5000))
+    r = a0 + sum(a / (x + s) for a, s in zip(al, sh))
+    assert np.max(np.abs(np.sqrt(x) * r - 1)) <= delta * (1 + 1e-6)
+
+
+def test_oracle_rational_apply_matches_dense_inverse_sqrt():
+    dims = (4, 4, 4, 4)
+    F, L = synth.hisq_links(dims, 99, 0.5)
+    mass = 0.1
+    b = synth.gaussian_source(dims, 7, 1, parity=0)[0]
+    exact, lo, hi = R.dense_power(dims, F, L, mass, b, -0.5)
+    assert lo >= 4 * mass * mass * (1 - 1e-12)
+    a0, al, sh, delta = R.zolotarev_inv_sqrt(lo, hi, 8)
+    got = R.rational_apply(dims, F, L, mass, a0, al, sh, b)
+    err = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+    assert err <= delta * (1 + 1e-6) + 1e-10
+    # fewer poles: the error grows but stays inside its own bound
+    a0, al, sh, delta3 = R.zolotarev_inv_sqrt(lo, hi, 3)
+    got3 = R.rational_apply(dims, F, L, mass, a0, al, sh, b)
+    err3 = np.linalg.norm(got3 - exact) / np.linalg.norm(exact)
+    assert err < err3 <= delta3 * (1 + 1e-6) + 1e-10
+
+
+def test_oracle_rational_apply_single_pole_is_inverse():
+    dims = (4, 4, 4, 4)
+    F, L = synth.hisq_links(dims, 99, 0.5)
+    mass = 0.1
+    b = synth.gaussian_source(dims, 8, 1, parity=0)[0]
+    inv, _, _ = R.dense_power(dims, F, L, mass, b, -1.0)
+    got = R.rational_apply(dims, F, L, mass, 0.0, [1.0], [0.0], b)
+    assert np.linalg.norm(got - inv) / np.linalg.norm(inv) < 1e-10
+
+
+@pytest.mark.parametrize("n,ratio", CASES + [(16, 1e10)])
+def test_library_zolotarev_matches_oracle(n, ratio):
+    from paper_2111_10354_amd import hisq
+    lmin = 2e-3
+    a0, al, sh, delta = hisq.zolotarev_inv_sqrt(lmin, lmin * ratio, n)
+    o0, oal, osh, od = R.zolotarev_inv_sqrt(lmin, lmin * ratio, n)
+    tol = 1e-6 if ratio > 1e8 else 1e-8
+    assert abs(a0 / o0 - 1) < tol
+    assert np.max(np.abs(np.array(sh) / osh - 1)) < tol
+    assert np.max(np.abs(np.array(al) / oal - 1)) < tol
+    assert abs(delta / od - 1) < 1e-5
+
+
+@pytest.mark.parametrize("args", [(0.0, 1.0, 4), (1.0, 0.5, 4), (1.0, 2.0, 0), (1.0, 2.0, 65), (1e-10, 1e5, 4),
+                                  (float("nan"), 1.0, 4)])
+def test_library_zolotarev_rejects(args):
+    from paper_2111_10354_amd import hisq
+    with pytest.raises(hisq.HisqError):
+        hisq.zolotarev_inv_sqrt(*args)
