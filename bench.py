@@ -100,6 +100,8 @@ def main():
                     help="autotuner cache (JSON lines); shapes found there are used without timing")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 48^3x12 multi-RHS sweep")
     ap.add_argument("--no-c3", action="store_true", help="skip the 48^3x12 batched and multi-shift solves")
+    ap.add_argument("--c3-solvers", action="store_true",
+                    help="only the 48^3x12 solves (plain, mixed, 16-RHS batched, 12-shift, A^(-1/2))")
     ap.add_argument("--fields-cache", type=str, default=None,
                     help="directory to save / reuse the generated link fields (profiling re-runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -122,6 +124,12 @@ def main():
         sys.exit(2)
 
     import synth  # input generator only
+    if args.c3_solvers:
+        import torch
+        from paper_2111_10354_amd import hisq
+        tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
+        print(json.dumps(run_c3_solvers(hisq, torch, tune)), flush=True)
+        return
     if args.c5_solve:
         # minutes-long solves: the library reports progress every 2000 iterations
         os.environ.setdefault("HISQ_SOLVER_TRACE", "1")
