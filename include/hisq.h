@@ -151,8 +151,10 @@ int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, co
                           void *out, const double *diag, const void *y, void *stream);
 
 /*
- * Autotune the Dslash launch shape (RHS tile per thread, block size, order in
- * which the 64-site tiles are processed) for the kernels a solve in `prec`
+ * Autotune the Dslash launch shape (RHS tile per thread: 1, 2, 4, 8 or 16, at
+ * most 4 with FP64 links; block size 64, 128 or 256; order in which the
+ * 64-site tiles are processed: memory order, t-fastest planes, or XCD bricks
+ * 2 | BY << 8 | BZ << 16) for the kernels a solve in `prec`
  * with `nrhs` right-hand sides launches: plain and epilogue Dslash in `prec`
  * and, if FP64 links are packed, the FP64 kernels of the reliable updates.
  * Each candidate must write bit-identical output to the default shape before

@@ -131,7 +131,7 @@ static std::vector<int> brick_orders(const Geom &G, int fi, int tile) {
 }
 
 static bool valid_shape(const Geom &geom, int fl, int nrhs, const DslashShape &s) {
-    if (s.tile < 1 || s.tile > 8 || (s.tile & (s.tile - 1)) || s.tile > std::max(1, nrhs)) return false;
+    if (s.tile < 1 || s.tile > 16 || (s.tile & (s.tile - 1)) || s.tile > std::max(1, nrhs)) return false;
     if (fl == F64 && s.tile > 4) return false;
     if (s.block != 64 && s.block != 128 && s.block != 256) return false;
     return order_supported(geom, s.order, s.block);
@@ -196,7 +196,7 @@ int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, con
     if ((rc = launch(ref_shape, ref.p))) return rc;
 
     std::vector<DslashShape> cands;
-    for (int tile : {1, 2, 4, 8})
+    for (int tile : {1, 2, 4, 8, 16})
         for (int block : {64, 128, 256})
             for (int order : brick_orders(G, fi, tile)) {
                 DslashShape c;

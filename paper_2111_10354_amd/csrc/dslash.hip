@@ -179,6 +179,8 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                     }
                 }
             };
+            // (a chunk's fat and long slots in separate loop trips halve the
+            // registers but measured 5-10 % slower: fewer gathers in flight)
             if constexpr (TILE == 1) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) chunk(c);
@@ -266,6 +268,14 @@ static int launch_tile(const Geom &g, const DslashLaunch &a, hipStream_t s) {
             if constexpr (LF != F64) {
                 launch_one<LF, SI, SO, 8, EPI>(g, a, s);
                 return 0;
+            }
+            [[fallthrough]];
+        case 16:
+            if constexpr (LF != F64) {
+                if (a.tile == 16) {
+                    launch_one<LF, SI, SO, 16, EPI>(g, a, s);
+                    return 0;
+                }
             }
             [[fallthrough]];
         default: return -1;

@@ -187,18 +187,18 @@ def test_multi_rhs_shifted_epilogue(gauges, prec):
 @pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 def test_ragged_rhs_tiles(tmp_path, cuda_device, prec, full):
-    """9 RHS in tiles of 2, 4 and 8 (the last tile ragged: its missing RHS
+    """17 RHS in tiles of 2, 4, 8 and 16 (the last tile ragged: its missing RHS
     repeat the last one and are never stored), plain and with the (A + sigma_i)
     epilogue: every tile writes exactly what one RHS per thread writes, and
-    nothing beyond the 9 outputs."""
+    nothing beyond the 17 outputs."""
     import torch
     dims = (10, 6, 4, 8)
     F, L = fields(dims)
     g = make_gauge(dims, F, L, full_links=full)
     vh = synth.volume(dims) // 2
-    n = 9
+    n = 17
     mass = 0.1
-    diag = [4 * mass * mass + s for s in (0.0, 1e-3, 0.1, 1.0, 3.0, 0.02, 0.5, 2.0, 1e-4)]
+    diag = [4 * mass * mass + 0.05 * k * k for k in range(n)]
     srcs = synth.gaussian_source(dims, 97, n, parity=1, index0=30)
     raw = np.concatenate([encode(to_cb(dims, s, 1), prec) for s in srcs])
     ys = synth.gaussian_source(dims, 97, n, parity=0, index0=40)
@@ -219,7 +219,7 @@ def test_ragged_rhs_tiles(tmp_path, cuda_device, prec, full):
         return o[:nb * n], e[:nb * n]
 
     ref, ref_e = run((1, 64, 0))
-    tiles = (2, 4) if prec == "fp64" else (2, 4, 8)
+    tiles = (2, 4) if prec == "fp64" else (2, 4, 8, 16)
     for tile in tiles:
         got, got_e = run((tile, 128, 0))
         assert np.array_equal(got, ref), tile
