@@ -374,7 +374,8 @@ def run_cg(hisq, torch):
     bcb, _ = cb_gather(dims, b, 0)
     bd = torch.from_numpy(encode(bcb, "fp64")).cuda()
     out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, 1 Gaussian RHS, tol 1e-10 (true residual)"}
-    for name, sloppy in (("plain_fp64", "fp64"), ("mixed_fp32", "fp32"), ("mixed_fp16s", "fp16s")):
+    for name, sloppy in (("plain_fp64", "fp64"), ("mixed_fp32", "fp32"), ("mixed_fp16s", "fp16s"),
+                         ("mixed_fp16l", "fp16l")):
         prm = hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25)
         x = torch.zeros_like(bd)
         hisq.cg_solve(g, mass, 1, bd, x, hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25, max_iter=50))
@@ -387,7 +388,8 @@ def run_cg(hisq, torch):
                      "reliable_updates": st[0]["reliable_updates"],
                      "true_residual": st[0]["true_residual"]}
         log(f"CG {name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
-    best = min(("mixed_fp32", "mixed_fp16s"), key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
+    best = min(("mixed_fp32", "mixed_fp16s", "mixed_fp16l"),
+               key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
     out["chosen"] = best
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
     g.close()
@@ -406,10 +408,10 @@ def run_c3_solvers(hisq, torch, tune):
     vh = synth.volume(dims) // 2
     log(f"C3 solves {dims} m={mass}: generating fields")
     F, L = synth.hisq_links(dims, synth.CFG_IDS["c3"], c["eps"])
-    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32"))
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32", "fp16s"))
     del F, L
-    for p in ("fp64", "fp32"):
-        for k in (1, n, ns):
+    for p in ("fp64", "fp32", "fp16l"):
+        for k in (1,) if p == "fp16l" else (1, n, ns):
             hisq.autotune(g, p, k, tune)
     srcs = synth.gaussian_source(dims, synth.CFG_IDS["c3"], n, parity=0)
     b = torch.from_numpy(np.concatenate([encode(cb_gather(dims, s_, 0)[0], "fp64") for s_ in srcs])).cuda()
@@ -431,21 +433,22 @@ def run_c3_solvers(hisq, torch, tune):
                 "true_residual_max": max(v["true_residual"] for v in st)}
 
     b0 = b[:sb]
-    for name, sloppy in (("plain_fp64_1rhs", "fp64"), ("mixed_fp32_1rhs", "fp32")):
+    for name, sloppy in (("plain_fp64_1rhs", "fp64"), ("mixed_fp32_1rhs", "fp32"), ("mixed_fp16l_1rhs", "fp16l")):
         x = torch.zeros_like(b0)
         (rc, st), wall = timed(lambda: hisq.cg_solve(g, mass, 1, b0, x, hisq.solver_params(sloppy_prec=sloppy)),
                                lambda: hisq.cg_solve(g, mass, 1, b0, torch.zeros_like(b0),
                                                      hisq.solver_params(sloppy_prec=sloppy, max_iter=50)))
         out[name] = summary(rc, st, wall, 1)
         log(f"C3 {name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
-    x = torch.zeros_like(b)
-    (rc, st), wall = timed(lambda: hisq.cg_solve(g, mass, n, b, x, hisq.solver_params(sloppy_prec="fp32")),
-                           lambda: hisq.cg_solve(g, mass, n, b, torch.zeros_like(b),
-                                                 hisq.solver_params(sloppy_prec="fp32", max_iter=50)))
-    out[f"batched_mixed_fp32_{n}rhs"] = summary(rc, st, wall, n)
-    log(f"C3 batched mixed FP32, {n} RHS: {wall:.3f} s ({wall / n:.3f} s per RHS), "
-        f"max {out[f'batched_mixed_fp32_{n}rhs']['iterations_max']} it, "
-        f"worst true res {out[f'batched_mixed_fp32_{n}rhs']['true_residual_max']:.2e}")
+    for sl in ("fp32",):
+        x = torch.zeros_like(b)
+        (rc, st), wall = timed(lambda: hisq.cg_solve(g, mass, n, b, x, hisq.solver_params(sloppy_prec=sl)),
+                               lambda: hisq.cg_solve(g, mass, n, b, torch.zeros_like(b),
+                                                     hisq.solver_params(sloppy_prec=sl, max_iter=50)))
+        key = f"batched_mixed_{sl}_{n}rhs"
+        out[key] = summary(rc, st, wall, n)
+        log(f"C3 batched mixed {sl.upper()}, {n} RHS: {wall:.3f} s ({wall / n:.3f} s per RHS), "
+            f"max {out[key]['iterations_max']} it, worst true res {out[key]['true_residual_max']:.2e}")
     shifts = [float(v) for v in synth.shifted_ladder(ns)]
     xs = torch.zeros(ns * sb, dtype=torch.uint8, device="cuda")
     (rc, st), wall = timed(lambda: hisq.multishift_cg(g, mass, shifts, b0, xs),
@@ -575,7 +578,7 @@ def run_c5_solve(plain_rhs=1, with_fp16s=False):
     FP64 true residual.  Plain form: FP64 CG one RHS at a time (timed on the
     first `plain_rhs` RHS; the 4-RHS total is that time per RHS x 4, marked as
     such).  Chosen forms: the 4 RHS batched through the multi-RHS Dslash with
-    FP32 or FP16S sloppy iterations and FP64 reliable updates."""
+    FP32 or (on request) FP16S sloppy iterations and FP64 reliable updates."""
     import torch
     import synth
     from paper_2111_10354_amd import hisq

@@ -71,6 +71,10 @@ extern "C" {
 #define HISQ_PREC_FP64 0
 #define HISQ_PREC_FP32 1
 #define HISQ_PREC_FP16S 2
+/* Solver sloppy precision only (hisq_solver_params.sloppy_prec, hisq_autotune,
+ * hisq_dslash_shape): the FP16 links of the FP16S copy applied to FP32
+ * vectors.  Needs the FP16S links packed. */
+#define HISQ_PREC_FP16L 3
 
 /* Bit masks for hisq_gauge_create's prec_mask. */
 #define HISQ_PREC_MASK(p) (1u << (p))
@@ -179,8 +183,10 @@ int hisq_dslash_shape(hisq_gauge_t g, int prec, int nrhs, int epilogue, int out[
 typedef struct {
     double tol;        /* target true relative residual |b - A x| / |b| (1e-10) */
     int max_iter;      /* iteration cap per right-hand side (100000) */
-    int sloppy_prec;   /* HISQ_PREC_FP64: plain CG; FP32 / FP16S: mixed precision
-                          with FP64 reliable updates (FP64) */
+    int sloppy_prec;   /* HISQ_PREC_FP64: plain CG; FP32 / FP16S / FP16L: mixed
+                          precision with FP64 reliable updates (FP64).  FP16S
+                          rounds the Krylov direction to FP16 as well, FP16L
+                          keeps every vector in FP32 and only the links in FP16 */
     int ru_period;     /* iterations between reliable updates (100) */
     int graph_chunk;   /* iterations per replay of a captured hipGraph; 0 = eager
                           kernel launches (32) */

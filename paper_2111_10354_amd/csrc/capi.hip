@@ -23,6 +23,8 @@ static int fail(int code, const std::string &msg) {
 }
 
 static bool valid_prec(int p) { return p == HISQ_PREC_FP64 || p == HISQ_PREC_FP32 || p == HISQ_PREC_FP16S; }
+// sloppy modes of the solvers: a spinor precision, or FP16 links with FP32 vectors
+static bool valid_sloppy(int p) { return valid_prec(p) || p == HISQ_PREC_FP16L; }
 
 static int check_dims(const int *dims) {
     if (!dims) return fail(HISQ_ERR_INVALID, "dims is NULL");
@@ -52,7 +54,7 @@ static int check_handle(hisq_gauge_t g) {
 static int check_params(const hisq_solver_params &p) {
     if (!(p.tol > 0.0) || !std::isfinite(p.tol)) return fail(HISQ_ERR_INVALID, "tol must be positive");
     if (p.max_iter < 1) return fail(HISQ_ERR_INVALID, "max_iter must be >= 1");
-    if (!valid_prec(p.sloppy_prec)) return fail(HISQ_ERR_INVALID, "bad sloppy_prec");
+    if (!valid_sloppy(p.sloppy_prec)) return fail(HISQ_ERR_INVALID, "bad sloppy_prec");
     if (p.graph_chunk < 0 || p.graph_chunk > 4096) return fail(HISQ_ERR_INVALID, "graph_chunk out of range");
     return HISQ_OK;
 }
@@ -345,15 +347,16 @@ int hisq_autotune(hisq_gauge_t g, int prec, int nrhs, const char *cache_path, vo
     TraceRange tr_("hisq_autotune");
     int rc = check_handle(g);
     if (rc) return rc;
-    if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
+    if (!valid_sloppy(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
     if (nrhs < 1 || nrhs > 64) return fail(HISQ_ERR_INVALID, "nrhs must be in 1..64");
-    if (!g->links[prec][0].p) return fail(HISQ_ERR_UNSUPPORTED, "links of this precision were not packed");
+    const int fl = sloppy_link_fmt(prec), fv = sloppy_vec_fmt(prec);
+    if (!g->links[fl][0].p) return fail(HISQ_ERR_UNSUPPORTED, "links of this precision were not packed");
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g->mu);
-    const int fq = prec == H16 ? F32 : prec;
+    const int fq = fv == H16 ? F32 : fv;
     struct Job { int fl, fi, fo; bool epi; };
-    std::vector<Job> jobs = {{prec, prec, prec, false}, {prec, prec, fq, true}};
-    if (fq != prec) jobs.push_back({prec, prec, prec, true});
+    std::vector<Job> jobs = {{fl, fv, fv, false}, {fl, fv, fq, true}};
+    if (fq != fv) jobs.push_back({fl, fv, fv, true});
     if (prec != F64 && g->links[F64][0].p) {  // FP64 kernels of the reliable updates
         jobs.push_back({F64, F64, F64, false});
         jobs.push_back({F64, F64, F64, true});
@@ -366,10 +369,11 @@ int hisq_autotune(hisq_gauge_t g, int prec, int nrhs, const char *cache_path, vo
 int hisq_dslash_shape(hisq_gauge_t g, int prec, int nrhs, int epilogue, int out[3]) {
     int rc = check_handle(g);
     if (rc) return rc;
-    if (!valid_prec(prec) || nrhs < 1 || epilogue < 0 || epilogue > 2 || !out)
+    if (!valid_sloppy(prec) || nrhs < 1 || epilogue < 0 || epilogue > 2 || !out)
         return fail(HISQ_ERR_INVALID, "bad arguments");
-    const int fo = (epilogue == 2 && prec == H16) ? F32 : prec;
-    const DslashShape sh = pick_shape(g, prec, prec, fo, nrhs, epilogue != 0);
+    const int fl = sloppy_link_fmt(prec), fv = sloppy_vec_fmt(prec);
+    const int fo = (epilogue == 2 && fv == H16) ? F32 : fv;
+    const DslashShape sh = pick_shape(g, fl, fv, fo, nrhs, epilogue != 0);
     out[0] = sh.tile;
     out[1] = sh.block;
     out[2] = sh.order;

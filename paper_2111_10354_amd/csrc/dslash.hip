@@ -320,6 +320,8 @@ int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s) {
         rc = launch_epi<H16, H16, H16>(g, a, s);
     else if (a.fmt_links == H16 && a.fmt_in == H16 && a.fmt_out == F32)
         rc = launch_epi<H16, H16, F32>(g, a, s);
+    else if (a.fmt_links == H16 && a.fmt_in == F32 && a.fmt_out == F32)
+        rc = launch_epi<H16, F32, F32>(g, a, s);
     if (rc != 0) {
         set_error("dslash: unsupported precision / tile combination");
         return HISQ_ERR_UNSUPPORTED;

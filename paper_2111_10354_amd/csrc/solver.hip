@@ -124,14 +124,14 @@ int nb_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int n, bool epi) {
 
 // One CG iteration for every running RHS of the workspace.
 static int cg_iteration(hisq_gauge_s *g, CgWorkspace &w, hipStream_t s) {
-    const int S = w.fmt, n = w.n, vh = g->geom.vh;
+    const int S = w.fmt, LF = w.lfmt, n = w.n, vh = g->geom.vh;
     const int fq = (S == H16) ? F32 : S;
     int rc;
-    if ((rc = gauge_dslash(g, 1, S, S, S, n, w.P(), w.T(), nullptr, nullptr, nullptr, w.st(), s))) return rc;
-    if ((rc = gauge_dslash(g, 0, S, S, fq, n, w.T(), w.Q(), w.P(), (const double *)w.diag.p,
+    if ((rc = gauge_dslash(g, 1, LF, S, S, n, w.P(), w.T(), nullptr, nullptr, nullptr, w.st(), s))) return rc;
+    if ((rc = gauge_dslash(g, 0, LF, S, fq, n, w.T(), w.Q(), w.P(), (const double *)w.diag.p,
                            (double *)w.part.p, w.st(), s)))
         return rc;
-    launch_reduce(RED_ALPHA, n, (double *)w.part.p, nb_dslash(g, S, S, fq, n, true), w.st(), nullptr, s);
+    launch_reduce(RED_ALPHA, n, (double *)w.part.p, nb_dslash(g, LF, S, fq, n, true), w.st(), nullptr, s);
     launch_update_xr(S, vh, n, w.X(), w.R(), w.P(), w.Q(), w.st(), (double *)w.part.p, s);
     launch_reduce(RED_BETA, n, (double *)w.part.p, blas_blocks(vh), w.st(), nullptr, s);
     launch_update_p(S, vh, n, w.R(), w.P(), w.st(), CG_RUNNING, s);
@@ -190,8 +190,8 @@ static int run_chunk(hisq_gauge_s *g, CgWorkspace &w, int chunk, bool use_graph,
     return HISQ_OK;
 }
 
-static CgWorkspace *get_ws(hisq_gauge_s *g, int n, int fmt, int chunk, int *rc) {
-    auto key = std::make_tuple(n, fmt, chunk);
+static CgWorkspace *get_ws(hisq_gauge_s *g, int n, int fmt, int lfmt, int chunk, int *rc) {
+    auto key = std::make_tuple(n, fmt | lfmt << 4, chunk);
     auto it = g->cg_ws.find(key);
     if (it != g->cg_ws.end()) {
         *rc = HISQ_OK;
@@ -200,6 +200,7 @@ static CgWorkspace *get_ws(hisq_gauge_s *g, int n, int fmt, int chunk, int *rc) 
     std::unique_ptr<CgWorkspace> w(new CgWorkspace());
     *rc = ws_alloc(*w, g->geom, n, fmt);
     if (*rc) return nullptr;
+    w->lfmt = lfmt;
     CgWorkspace *p = w.get();
     g->cg_ws[key] = std::move(w);
     return p;
@@ -211,15 +212,15 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     const auto t0 = clk::now();
     const Geom &G = g->geom;
     const int vh = G.vh;
-    const int S = prm.sloppy_prec;
-    if (!g->links[F64][0].p || !g->links[S][0].p) {
+    const int S = sloppy_vec_fmt(prm.sloppy_prec), LF = sloppy_link_fmt(prm.sloppy_prec);
+    if (!g->links[F64][0].p || !g->links[LF][0].p) {
         set_error("cg: the handle lacks packed FP64 links or links of the sloppy precision");
         return HISQ_ERR_UNSUPPORTED;
     }
     const int chunk = std::max(1, prm.graph_chunk > 0 ? prm.graph_chunk : 8);
     const bool use_graph = prm.graph_chunk > 0;
     int rc;
-    CgWorkspace *wp = get_ws(g, n, S, use_graph ? chunk : 0, &rc);
+    CgWorkspace *wp = get_ws(g, n, S, LF, use_graph ? chunk : 0, &rc);
     if (!wp) return rc;
     CgWorkspace &w = *wp;
     const size_t s64 = spinor_bytes(F64, vh) * n;
@@ -331,8 +332,8 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
             o.true_residual = tr;
             o.wall_ms = ms;
             o.dslash_bytes = (double)c.iter *
-                                 (double)(dslash_algorithmic_bytes(S, S, S, vh, 1, false, g->compressed) +
-                                          dslash_algorithmic_bytes(S, S, S == H16 ? F32 : S, vh, 1, true, g->compressed)) +
+                                 (double)(dslash_algorithmic_bytes(LF, S, S, vh, 1, false, g->compressed) +
+                                          dslash_algorithmic_bytes(LF, S, S == H16 ? F32 : S, vh, 1, true, g->compressed)) +
                              (double)(c.reliable + 1) *
                                  (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
                                           dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed));

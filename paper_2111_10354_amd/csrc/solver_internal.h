@@ -79,6 +79,7 @@ struct DslashShape {
 // Buffers, device state and the captured iteration graph of one solver shape.
 struct CgWorkspace {
     int n = 0, fmt = F64, chunk = 0;
+    int lfmt = F64;  // links of the sloppy Dslash
     DevBuf b64, x64, r64, t64, ax64, p64, q64;
     DevBuf xs, rs, ps, ts, qs;
     DevBuf part, state, diag, scal;
@@ -126,12 +127,17 @@ struct hisq_gauge_s {
     std::mutex mu;
     // autotuned shapes keyed by (links fmt, in fmt, out fmt, nrhs, epilogue)
     std::map<std::tuple<int, int, int, int, int>, hisq::DslashShape> shapes;
-    std::map<std::tuple<int, int, int>, std::unique_ptr<hisq::CgWorkspace>> cg_ws;  // (n, fmt, chunk)
+    std::map<std::tuple<int, int, int>, std::unique_ptr<hisq::CgWorkspace>> cg_ws;  // (n, fmt | links << 4, chunk)
     std::unique_ptr<hisq::FcgWorkspace> fcg_ws;
     ~hisq_gauge_s();
 };
 
 namespace hisq {
+
+// Link and vector formats of a solver sloppy mode (HISQ_PREC_FP16L: FP16
+// links applied to FP32 vectors; otherwise both in the named precision).
+inline int sloppy_link_fmt(int sloppy) { return sloppy == HISQ_PREC_FP16L ? H16 : sloppy; }
+inline int sloppy_vec_fmt(int sloppy) { return sloppy == HISQ_PREC_FP16L ? F32 : sloppy; }
 
 // The FP64 copy always keeps every link whole: it carries the true residual
 // and the reliable updates, where a 1e-15 row-rebuild error times the

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhisq.so")
 
 PREC_FP64, PREC_FP32, PREC_FP16S = 0, 1, 2
-PREC_NAMES = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16s": PREC_FP16S}
+PREC_FP16L = 3  # solver sloppy mode only: FP16 links applied to FP32 vectors
+PREC_NAMES = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp16s": PREC_FP16S, "fp16l": PREC_FP16L}
 
 OK, ERR_INVALID, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 NOT_CONVERGED, BREAKDOWN, CONVERGED_AFTER_FALLBACK = 1, 2, 3

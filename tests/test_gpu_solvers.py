@@ -44,7 +44,7 @@ def solve(g, dims, mass, srcs, **kw):
     return rc, st, sol
 
 
-@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s", "fp16l"])
 @pytest.mark.parametrize("graph_chunk", [0, 16])
 def test_cg_c1(c1, sloppy, graph_chunk):
     dims, F, L, g = c1
@@ -82,7 +82,7 @@ def test_mixed_precision_low_mass():
     g = make_gauge(dims, F, L)
     mass = 0.01
     b = synth.gaussian_source(dims, 99, 1, parity=0)[0]
-    for sloppy in ("fp64", "fp32", "fp16s"):
+    for sloppy in ("fp64", "fp32", "fp16s", "fp16l"):
         flush(f"cg 8^4 m=0.01 sloppy={sloppy}")
         rc, st, (x,) = solve(g, dims, mass, [b], sloppy_prec=sloppy)
         assert rc == 0, st
@@ -90,7 +90,7 @@ def test_mixed_precision_low_mass():
     g.close()
 
 
-@pytest.mark.parametrize("sloppy", ["fp32", "fp16s"])
+@pytest.mark.parametrize("sloppy", ["fp32", "fp16s", "fp16l"])
 def test_mixed_precision_very_low_mass(sloppy):
     """m = 0.002 (the 96^3 x 24 workload's mass): the sloppy iteration must not
     stall at the tolerance, where its iterated residual keeps claiming
@@ -120,7 +120,7 @@ def test_batched_multi_rhs(c1):
     dims, F, L, g = c1
     mass = 0.1
     srcs = synth.gaussian_source(dims, 0, 3, parity=0, index0=30)
-    for sloppy in ("fp64", "fp32"):
+    for sloppy in ("fp64", "fp32", "fp16l"):
         rc, st, xs = solve(g, dims, mass, list(srcs), sloppy_prec=sloppy)
         assert rc == 0
         for b, x, s in zip(srcs, xs, st):
