@@ -93,3 +93,21 @@ def test_library_zolotarev_rejects(args):
     from paper_2111_10354_amd import hisq
     with pytest.raises(hisq.HisqError):
         hisq.zolotarev_inv_sqrt(*args)
+
+
+def test_golden_zolotarev_coefficients():
+    """tests/golden/zolotarev_inv_sqrt_n8.json was written by
+    tests/golden/make_golden.py from the oracle alone: the oracle still
+    reproduces it, and the library's host routine agrees with it."""
+    import json
+    import os
+    from paper_2111_10354_amd import hisq
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "zolotarev_inv_sqrt_n8.json")
+    rec = json.load(open(path))
+    o0, oal, osh, od = R.zolotarev_inv_sqrt(rec["lmin"], rec["lmax"], rec["npole"])
+    assert o0 == pytest.approx(rec["alpha0"], rel=1e-12)
+    assert np.allclose(oal, rec["alpha"], rtol=1e-12) and np.allclose(osh, rec["shift"], rtol=1e-12)
+    a0, al, sh, delta = hisq.zolotarev_inv_sqrt(rec["lmin"], rec["lmax"], rec["npole"])
+    assert a0 == pytest.approx(rec["alpha0"], rel=1e-9)
+    assert np.allclose(al, rec["alpha"], rtol=1e-9) and np.allclose(sh, rec["shift"], rtol=1e-9)
+    assert delta == pytest.approx(rec["delta"], rel=1e-5)
