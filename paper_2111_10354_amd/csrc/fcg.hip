@@ -208,7 +208,11 @@ FcgWorkspace::~FcgWorkspace() {
 }
 
 static int fcg_ws_get(hisq_gauge_s *g, FcgWorkspace **out) {
-    if (!g->fcg_ws) g->fcg_ws.reset(new FcgWorkspace());
+    if (!g->fcg_ws) g->fcg_ws.reset(new (std::nothrow) FcgWorkspace());
+    if (!g->fcg_ws) {
+        set_error("flexible CG: host allocation failed");
+        return HISQ_ERR_OOM;
+    }
     FcgWorkspace &w = *g->fcg_ws;
     const int vh = g->geom.vh;
     const size_t s64 = spinor_bytes(F64, vh), s32 = spinor_bytes(F32, vh);

@@ -23,7 +23,11 @@ enum { MODE_HIDDEN = 0, MODE_EVEN = 1 };
 
 int nn_create(hisq_nn_s **out, hisq_gauge_s *g, int nlayers, const int *ch, const double *weights, hipStream_t s) {
     static std::atomic<unsigned long long> next_id{1};
-    hisq_nn_s *n = new hisq_nn_s();
+    hisq_nn_s *n = new (std::nothrow) hisq_nn_s();
+    if (!n) {
+        set_error("network: host allocation failed");
+        return HISQ_ERR_OOM;
+    }
     n->id = next_id++;
     n->gauge = g;
     n->nlayers = nlayers;

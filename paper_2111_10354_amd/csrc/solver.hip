@@ -197,7 +197,12 @@ static CgWorkspace *get_ws(hisq_gauge_s *g, int n, int fmt, int lfmt, int chunk,
         *rc = HISQ_OK;
         return it->second.get();
     }
-    std::unique_ptr<CgWorkspace> w(new CgWorkspace());
+    std::unique_ptr<CgWorkspace> w(new (std::nothrow) CgWorkspace());
+    if (!w) {
+        set_error("cg: host allocation failed");
+        *rc = HISQ_ERR_OOM;
+        return nullptr;
+    }
     *rc = ws_alloc(*w, g->geom, n, fmt);
     if (*rc) return nullptr;
     w->lfmt = lfmt;
