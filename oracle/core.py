@@ -23,8 +23,10 @@ def library_path() -> str:
 def _lib():
     global _LIB
     if _LIB is None:
-        path = _build.OUT
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        # HISQ_ORACLE_LIB: a differently built oracle (the mutation tests load
+        # copies with planted mistakes through it)
+        path = os.environ.get("HISQ_ORACLE_LIB") or _build.OUT
+        if path == _build.OUT and (not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
             _build.build(force=True, quiet=True)
         lib = C.CDLL(path)
         dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
