@@ -277,12 +277,30 @@ def main():
                "sample": f"{reps} full single-parity FP64 Dslash applications on the same {dims} lattice "
                          f"({t_one:.2f} s each); GB/s counts the FP64 algorithmic bytes (2400 B/site)"}
         log(f"oracle: {t_one:.2f} s per Dslash = {cpu['value']:.2f} GB/s")
+        # the oracle's plain FP64 CG on the 32^3 x 8 workload: 200 iterations
+        # timed, the time to solution extrapolated to the GPU's iteration count
+        c2 = synth.CONFIGS["c2"]
+        F2, L2 = synth.hisq_links(c2["dims"], synth.CFG_IDS["c2"], c2["eps"])
+        b2 = synth.gaussian_source(c2["dims"], synth.CFG_IDS["c2"], 1, parity=0)[0]
+        t1 = time.time()
+        _, _, it2, _ = oracle.cg(c2["dims"], F2, L2, c2["mass"], b2, tol=1e-10, max_iter=200)
+        per_it = (time.time() - t1) / max(it2, 1)
+        cpu["cg_32x32x32x8"] = {"seconds_per_iteration": per_it, "iterations_timed": it2,
+                                "note": "plain FP64 CG of the oracle; time to solution = this x the GPU's "
+                                        "plain-CG iteration count (extrapolated)"}
+        log(f"oracle CG 32^3x8: {1e3 * per_it:.1f} ms per iteration ({it2} timed)")
+        del F2, L2
     del F, L
 
     # ---- CG time to solution on the 32^3 x 8 workload
     cg = None
     if not (args.quick or args.no_cg):
         cg = run_cg(hisq, torch)
+        if cpu is not None and "cg_32x32x32x8" in cpu:
+            oc = cpu["cg_32x32x32x8"]
+            oc["extrapolated_seconds_to_solution"] = oc["seconds_per_iteration"] * cg["plain_fp64"]["iterations"]
+            log(f"oracle CG 32^3x8 extrapolated to {cg['plain_fp64']['iterations']} iterations: "
+                f"{oc['extrapolated_seconds_to_solution']:.1f} s (GPU plain FP64 {cg['plain_fp64']['seconds']:.3f} s)")
 
     # ---- batched and multi-shift solves on the 48^3 x 12 workload
     c3 = None
