@@ -43,6 +43,9 @@ typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b4v __attribute__((ext_vector_type(4)));
 typedef unsigned int u2v __attribute__((ext_vector_type(2)));
 
+template <class T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+
 constexpr int NW_SITES = 32;                 // sites per wavefront
 constexpr int NW_COLS = 3 * NW_SITES;        // (site, colour) columns per wavefront
 constexpr int NN_WAVES = 2;                  // wavefronts per block
@@ -199,11 +202,7 @@ __device__ __forceinline__ void transport_hidden(const Lex &g, const void *thin,
                     for (int c = 0; c < 3; ++c) cmac(t, w[3 * a + c], vb[c]);
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {  // conj(U[c][a]) v[c]
-                        const cx<float> u = w[3 * c + a];
-                        t.re += u.re * vb[c].re + u.im * vb[c].im;
-                        t.im += u.re * vb[c].im - u.im * vb[c].re;
-                    }
+                    for (int c = 0; c < 3; ++c) cmac(t, cconj(w[3 * c + a]), vb[c]);  // conj(U[c][a]) v[c]
                 }
                 tr[a][q] = t.re;
                 ti[a][q] = t.im;
@@ -249,9 +248,7 @@ __device__ __forceinline__ void transport_even_path(const Lex &g, const void *th
                     if constexpr (P <= 4) {
                         cmac(t[a], w[3 * a + c], v[c]);
                     } else {
-                        const cx<float> u = w[3 * c + a];
-                        t[a].re += u.re * v[c].re + u.im * v[c].im;
-                        t[a].im += u.re * v[c].im - u.im * v[c].re;
+                        cmac(t[a], cconj(w[3 * c + a]), v[c]);
                     }
                 }
             }
