@@ -40,48 +40,6 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Processing order of the 64-site tiles (the low byte of `order`).
-//
-// 0: memory order (x, y, z, t).
-// 1: (z, t) planes with t fastest, which brings the time-direction neighbours
-//    16x closer in processing order.  Needs whole tiles per plane.
-// 2: XCD bricks.  Workgroup b runs on XCD b % 8 (workgroups are dealt to the
-//    eight XCDs in turn), so logical block (b % 8) * nb/8 + b/8 hands every XCD
-//    one contiguous eighth of the processing order and its own L2 sees every
-//    neighbour gather of that eighth.  The order walks columns of BY y-rows by
-//    BZ z-planes (BY = bits 8-15 of `order`, BZ = bits 16-23), with z-block
-//    slowest, then y-block, then t, then z inside the block, then the column's
-//    tiles.  While a column is swept along t, all sixteen hops of the sites in
-//    flight (+-1 and +-3 in every direction) fall inside a window of seven
-//    t-slices of the column, which is sized to stay in one L2; only the column
-//    faces are fetched twice.
-__device__ __forceinline__ int site_of_thread(const Geom &g, int blk, int nb, int tid, int order) {
-    const int kind = order & 0xff;
-    if (kind == 2) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-    const int i = blk * (int)blockDim.x + tid;
-    // grid tail: keep it out of range (the permutations below would map an
-    // index past the last tile back onto a valid one)
-    if (kind == 0 || i >= g.vh) return i;
-    const int tpp = (g.lxh * g.L[1]) >> 6;  // tiles per (z, t) plane
-    int wt = i >> 6;
-    if (kind == 1) {
-        const int q = wt / tpp, p = wt - q * tpp;
-        const int z = q / g.L[3], t = q - z * g.L[3];
-        return ((t * g.L[2] + z) * tpp + p) * 64 + (i & 63);
-    }
-    const int by = (order >> 8) & 0xff, bz = (order >> 16) & 0xff;
-    const int ty = (g.lxh * by) >> 6;  // tiles per column row block
-    const int nyb = g.L[1] / by;
-    const int within = wt % ty;
-    wt /= ty;
-    const int zz = wt % bz;
-    wt /= bz;
-    const int t = wt % g.L[3];
-    wt /= g.L[3];
-    const int yb = wt % nyb, zb = wt / nyb;
-    return ((t * g.L[2] + zb * bz + zz) * tpp + yb * ty + within) * 64 + (i & 63);
-}
-
 template <int LF, int SI, int SO, int TILE, bool EPI, bool COMP>
 __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restrict__ lptr, Spinor<SI> in,
                                                      Spinor<SO> out, Spinor<SI> y,
@@ -93,7 +51,7 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
     constexpr int G = LinkGroup<LF>::G;
     const int nb = gridDim.x;
     const int blk = blockIdx.x;
-    const int h = site_of_thread(g, blk, nb, threadIdx.x, order);
+    const int h = site_of_thread(g, blk, nb, (int)blockDim.x, threadIdx.x, order);
     const int r0 = blockIdx.y * TILE;
     if (skip) {
         bool idle = true;

@@ -50,7 +50,7 @@ struct Geom {
 
 Geom make_geom(const int dims[4]);
 
-__device__ __forceinline__ int wrap(int c, int L) {
+__host__ __device__ __forceinline__ int wrap(int c, int L) {
     c = c < 0 ? c + L : c;
     return c >= L ? c - L : c;
 }
@@ -59,7 +59,7 @@ struct SiteCoord {
     int x, y, z, t, base;  // base = h - (x >> 1)
 };
 
-__device__ __forceinline__ SiteCoord decode_site(const Geom &g, int h, int parity) {
+__host__ __device__ __forceinline__ SiteCoord decode_site(const Geom &g, int h, int parity) {
     SiteCoord s;
     int xh = h % g.lxh;
     int r = h / g.lxh;
@@ -73,7 +73,7 @@ __device__ __forceinline__ SiteCoord decode_site(const Geom &g, int h, int parit
 }
 
 // Index of the site reached by `d` steps along mu (|d| <= 3 < L_mu).
-__device__ __forceinline__ int hop_index(const Geom &g, const SiteCoord &s, int h, int mu, int d) {
+__host__ __device__ __forceinline__ int hop_index(const Geom &g, const SiteCoord &s, int h, int mu, int d) {
     switch (mu) {
         case 0: return s.base + (wrap(s.x + d, g.L[0]) >> 1);
         case 1: return h + (wrap(s.y + d, g.L[1]) - s.y) * g.sy;
@@ -83,7 +83,51 @@ __device__ __forceinline__ int hop_index(const Geom &g, const SiteCoord &s, int 
 }
 
 // Hop of link slot k = 4*mu + j: j = 0 -> +1, 1 -> -1, 2 -> +3, 3 -> -3.
-__device__ __forceinline__ constexpr int slot_dist(int j) { return j == 0 ? 1 : j == 1 ? -1 : j == 2 ? 3 : -3; }
+__host__ __device__ __forceinline__ constexpr int slot_dist(int j) { return j == 0 ? 1 : j == 1 ? -1 : j == 2 ? 3 : -3; }
+
+// Output site of thread `tid` of workgroup `blk` (of `nb`, `bdim` threads each)
+// in the processing order of the 64-site tiles (the low byte of `order`).
+//
+// 0: memory order (x, y, z, t).
+// 1: (z, t) planes with t fastest, which brings the time-direction neighbours
+//    16x closer in processing order.  Needs whole tiles per plane.
+// 2: XCD bricks.  Workgroup b runs on XCD b % 8 (workgroups are dealt to the
+//    eight XCDs in turn), so logical block (b % 8) * nb/8 + b/8 hands every XCD
+//    one contiguous eighth of the processing order and its own L2 sees every
+//    neighbour gather of that eighth.  The order walks columns of BY y-rows by
+//    BZ z-planes (BY = bits 8-15 of `order`, BZ = bits 16-23), with z-block
+//    slowest, then y-block, then t, then z inside the block, then the column's
+//    tiles.  While a column is swept along t, all sixteen hops of the sites in
+//    flight (+-1 and +-3 in every direction) fall inside a window of seven
+//    t-slices of the column, which is sized to stay in one L2; only the column
+//    faces are fetched twice.
+__host__ __device__ __forceinline__ int site_of_thread(const Geom &g, int blk, int nb, int bdim, int tid,
+                                                       int order) {
+    const int kind = order & 0xff;
+    if (kind == 2) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    const int i = blk * bdim + tid;
+    // grid tail: keep it out of range (the permutations below would map an
+    // index past the last tile back onto a valid one)
+    if (kind == 0 || i >= g.vh) return i;
+    const int tpp = (g.lxh * g.L[1]) >> 6;  // tiles per (z, t) plane
+    int wt = i >> 6;
+    if (kind == 1) {
+        const int q = wt / tpp, p = wt - q * tpp;
+        const int z = q / g.L[3], t = q - z * g.L[3];
+        return ((t * g.L[2] + z) * tpp + p) * 64 + (i & 63);
+    }
+    const int by = (order >> 8) & 0xff, bz = (order >> 16) & 0xff;
+    const int ty = (g.lxh * by) >> 6;  // tiles per column row block
+    const int nyb = g.L[1] / by;
+    const int within = wt % ty;
+    wt /= ty;
+    const int zz = wt % bz;
+    wt /= bz;
+    const int t = wt % g.L[3];
+    wt /= g.L[3];
+    const int yb = wt % nyb, zb = wt / nyb;
+    return ((t * g.L[2] + zb * bz + zz) * tpp + yb * ty + within) * 64 + (i & 63);
+}
 
 // ------------------------------------------------------------------ formats
 enum Fmt { F64 = HISQ_PREC_FP64, F32 = HISQ_PREC_FP32, H16 = HISQ_PREC_FP16S };
@@ -244,7 +288,7 @@ inline size_t link_parity_bytes(int f, int64_t vh, bool compressed = false) {
     return (size_t)tiles * (16 / link_group_size(f)) * 9 * 1024;
 }
 
-__device__ __forceinline__ const u4v *link_unit_ptr(const void *base, int ng, int gi, int h) {
+__host__ __device__ __forceinline__ const u4v *link_unit_ptr(const void *base, int ng, int gi, int h) {
     return (const u4v *)base + ((size_t)((h >> 6) * ng + gi) * 9) * 64 + (h & 63);
 }
 
@@ -298,7 +342,7 @@ template <> struct Links<H16> {
 template <int F> struct LinksC;
 
 template <int F>
-__device__ __forceinline__ const u4v *comp_unit_ptr(const void *base, int c, int h) {
+__host__ __device__ __forceinline__ const u4v *comp_unit_ptr(const void *base, int c, int h) {
     constexpr int NC = CompGeom<F>::NC, UC = CompGeom<F>::UF + CompGeom<F>::UL;
     return (const u4v *)base + ((size_t)((h >> 6) * NC + c) * UC) * 64 + (h & 63);
 }

@@ -1,0 +1,120 @@
+// Host-side check of the Dslash kernel's index arithmetic, built from the
+// kernel's own helpers (hisq_internal.h: site_of_thread, decode_site,
+// hop_index, link_unit_ptr, comp_unit_ptr are host + device).  For every
+// thread of the launch grids the kernel uses - block sizes 64, 128, 256, every
+// traversal order the launcher accepts - it checks that
+//  * the threads inside the lattice cover every output site exactly once;
+//  * the decoded coordinates give back the site and its parity;
+//  * each of the 16 hops lands on the site a coordinate-based reference gives,
+//    of the other parity, inside [0, Vh);
+//  * every 16-byte link unit a thread reads, whole or compressed layout, lies
+//    inside the packed buffer, and the sign word inside the sign plane.
+// Prints one line per lattice and exits non-zero on the first violation.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "hisq_internal.h"
+
+using namespace hisq;
+
+static int fails = 0;
+#define CHECK(cond, ...)                                  \
+    do {                                                  \
+        if (!(cond)) {                                    \
+            std::fprintf(stderr, __VA_ARGS__);            \
+            std::fprintf(stderr, "\n");                   \
+            if (++fails > 20) std::exit(1);               \
+        }                                                 \
+    } while (0)
+
+static long lex_of(const int L[4], const int c[4]) { return c[0] + (long)L[0] * (c[1] + (long)L[1] * (c[2] + (long)L[2] * c[3])); }
+
+// units of 16 bytes in one parity's packed links
+static long whole_units(int f, long vh) { return (long)link_parity_bytes(f, vh, false) / 16; }
+static long comp_units_total(int f, long vh) { return (long)link_parity_bytes(f, vh, true) / 16; }
+
+static void check_lattice(const int dims[4], bool quick) {
+    const Geom g = make_geom(dims);
+    const long vh = g.vh;
+    std::vector<int> orders = {0, 1};
+    for (int by : {4, 8, 12, 16, 24})
+        for (int bz : {2, 4, 8, 12, 16}) orders.push_back(2 | by << 8 | bz << 16);
+    long launches = 0;
+    for (int parity = 0; parity < 2; ++parity) {
+        for (int block : {64, 128, 256}) {
+            const int nb = (int)((vh + block - 1) / block);
+            for (int order : orders) {
+                if (!order_supported(g, order, block)) continue;
+                if (quick && order > 1 && order != orders[2 + 7]) continue;
+                ++launches;
+                std::vector<unsigned char> seen(vh, 0);
+                for (int blk = 0; blk < nb; ++blk)
+                    for (int tid = 0; tid < block; ++tid) {
+                        const int h = site_of_thread(g, blk, nb, block, tid, order);
+                        if (h >= vh) continue;  // grid tail, skipped by the kernel's guard
+                        CHECK(h >= 0, "negative site %d (order %d block %d)", h, order, block);
+                        CHECK(!seen[h], "site %d twice (order %d block %d)", h, order, block);
+                        seen[h] = 1;
+                    }
+                for (long h = 0; h < vh; ++h) CHECK(seen[h], "site %ld never visited (order %d block %d)", h, order, block);
+            }
+        }
+        // geometry and hops (independent of the launch shape)
+        for (long h = 0; h < vh; ++h) {
+            const SiteCoord sc = decode_site(g, (int)h, parity);
+            const int c[4] = {sc.x, sc.y, sc.z, sc.t};
+            const long lex = lex_of(dims, c);
+            CHECK((lex >> 1) == h && ((c[0] + c[1] + c[2] + c[3]) & 1) == parity, "decode of site %ld parity %d", h, parity);
+            for (int k = 0; k < 16; ++k) {
+                const int mu = k >> 2, d = slot_dist(k & 3);
+                const int nbh = hop_index(g, sc, (int)h, mu, d);
+                int cn[4] = {c[0], c[1], c[2], c[3]};
+                cn[mu] = ((cn[mu] + d) % dims[mu] + dims[mu]) % dims[mu];
+                const long ref = lex_of(dims, cn);
+                CHECK(nbh >= 0 && nbh < vh, "hop out of range: site %ld slot %d -> %d", h, k, nbh);
+                CHECK(nbh == (ref >> 1) && ((cn[0] + cn[1] + cn[2] + cn[3]) & 1) == 1 - parity,
+                      "hop of site %ld slot %d: %d, reference %ld", h, k, nbh, ref >> 1);
+            }
+            // link units of the site: whole layout (groups of 1, 2, 4 slots)
+            for (int f : {F64, F32, H16}) {
+                const int G = f == F64 ? 1 : f == F32 ? 2 : 4, ng = 16 / G;
+                for (int gi = 0; gi < ng; ++gi) {
+                    const long u = (long)(link_unit_ptr(nullptr, ng, gi, (int)h) - (const u4v *)nullptr);
+                    CHECK(u >= 0 && u + 8 * 64 < whole_units(f, vh), "whole link unit %ld of site %ld fmt %d", u, h, f);
+                }
+            }
+            // compressed layout (FP32 and FP16) and its sign word
+            {
+                constexpr int NC = CompGeom<F32>::NC, UC = CompGeom<F32>::UF + CompGeom<F32>::UL;
+                for (int cc = 0; cc < NC; ++cc) {
+                    const long u = (long)(comp_unit_ptr<F32>(nullptr, cc, (int)h) - (const u4v *)nullptr);
+                    CHECK(u >= 0 && u + (UC - 1) * 64 < comp_units_total(F32, vh), "compressed FP32 unit of site %ld", h);
+                }
+                const long tiles = (vh + LINK_TILE - 1) / LINK_TILE;
+                CHECK((long)(tiles * comp_units_per_site(F32) * 1024) + 4 * (h + 1) <= (long)link_parity_bytes(F32, vh, true),
+                      "FP32 sign word of site %ld", h);
+            }
+            {
+                constexpr int NC = CompGeom<H16>::NC, UC = CompGeom<H16>::UF + CompGeom<H16>::UL;
+                for (int cc = 0; cc < NC; ++cc) {
+                    const long u = (long)(comp_unit_ptr<H16>(nullptr, cc, (int)h) - (const u4v *)nullptr);
+                    CHECK(u >= 0 && u + (UC - 1) * 64 < comp_units_total(H16, vh), "compressed FP16 unit of site %ld", h);
+                }
+            }
+        }
+    }
+    std::printf("%dx%dx%dx%d: Vh %ld, %ld launch shapes, %s\n", dims[0], dims[1], dims[2], dims[3], vh, launches,
+                fails ? "FAILED" : "ok");
+}
+
+int main(int argc, char **argv) {
+    const int lattices[][4] = {{4, 4, 4, 4}, {6, 4, 4, 10}, {10, 6, 4, 8}, {8, 8, 8, 8}, {16, 8, 8, 8},
+                               {8, 12, 8, 16}, {16, 16, 16, 8}, {32, 32, 32, 8}, {48, 48, 48, 12}};
+    for (const auto &d : lattices) check_lattice(d, false);
+    if (argc > 1) {  // the benchmark lattice: Vh = 10.6 M, one traversal order per kind
+        const int big[4] = {96, 96, 96, 24};
+        check_lattice(big, true);
+    }
+    return fails ? 1 : 0;
+}
