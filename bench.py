@@ -418,8 +418,9 @@ def run_c3_solvers(hisq, torch, tune):
     """48^3 x 12, m = 0.005: one RHS by plain FP64 CG and by mixed FP32 CG, all
     16 RHS batched through the multi-RHS Dslash (mixed FP32, FP64 reliable
     updates), the 12-shift ladder sigma_k = 10^(-4 + 4k/11) by multi-shift CG,
-    and A^(-1/2) b by a 16-pole Zolotarev approximation; every solve to the
-    1e-10 FP64 true residual."""
+    and the two-flavour pseudofermion heat bath phi = A^(1/4) eta (16 Remez
+    poles) and action phi^+ A^(-1/2) phi (16 Zolotarev poles); every solve to
+    the 1e-10 FP64 true residual."""
     import synth
     c = synth.CONFIGS["c3"]
     dims, mass, n, ns = c["dims"], c["mass"], c["nrhs"], c["nshift"]
@@ -478,24 +479,42 @@ def run_c3_solvers(hisq, torch, tune):
     out[f"multishift_fp64_{ns}shifts"] = ms
     log(f"C3 multi-shift, {ns} shifts: {wall:.3f} s, base {ms['iterations_base']} it, "
         f"worst true res {ms['true_residual_max']:.2e}")
-    # rooted-staggered pseudofermion operator A^(-1/2) b: Zolotarev poles on
-    # [4 m^2, 1.05 x the power-iteration estimate of the top eigenvalue]
+    # rooted-staggered pseudofermions for two flavours on [4 m^2, 1.05 x the
+    # power-iteration estimate of the top eigenvalue]: heat bath phi = A^(1/4) eta
+    # (Remez coefficients), then the action phi^+ A^(-1/2) phi (Zolotarev), which
+    # returns |eta|^2 up to the two approximation errors
     t1 = time.time()
     lo, hi = hisq.spectral_bounds(g, mass, 100)
     t_bounds = time.time() - t1
     npole = 16
+    t1 = time.time()
+    h0, hal, hsh, hdelta = hisq.rational_remez(0.25, lo, 1.05 * hi, npole)
+    t_remez = time.time() - t1
+    phi = torch.empty_like(b0)
+    (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, h0, hal, hsh, b0, phi),
+                           lambda: hisq.rational_apply(g, mass, h0, hal, hsh, b0, torch.empty_like(b0),
+                                                       hisq.solver_params(max_iter=50)))
+    out[f"heatbath_quarter_root_remez_{npole}poles"] = {
+        "status": rc, "seconds": round(wall, 4), "remez_seconds": round(t_remez, 4),
+        "approximation_rel_error": hdelta, "iterations_base": st[0]["iterations"],
+        "true_residual_max": max(v["true_residual"] for v in st)}
+    log(f"C3 heat bath A^(1/4) eta, {npole} Remez poles (rel. error {hdelta:.1e}, coefficients {t_remez:.3f} s): "
+        f"{wall:.3f} s, base {st[0]['iterations']} it")
     a0, al, sh, delta = hisq.zolotarev_inv_sqrt(lo, 1.05 * hi, npole)
     y = torch.empty_like(b0)
-    (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, a0, al, sh, b0, y),
-                           lambda: hisq.rational_apply(g, mass, a0, al, sh, b0, torch.empty_like(b0),
+    (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, y),
+                           lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, torch.empty_like(b0),
                                                        hisq.solver_params(max_iter=50)))
-    action = float(torch.dot(b0.view(torch.float64), y.view(torch.float64)))
+    action = float(torch.dot(phi.view(torch.float64), y.view(torch.float64)))
+    eta2 = float(torch.dot(b0.view(torch.float64), b0.view(torch.float64)))
     out[f"inv_sqrt_zolotarev_{npole}poles"] = {
         "status": rc, "seconds": round(wall, 4), "spectral_bounds": [lo, hi], "bounds_seconds": round(t_bounds, 4),
         "approximation_rel_error": delta, "iterations_base": st[0]["iterations"],
-        "true_residual_max": max(v["true_residual"] for v in st), "pseudofermion_action": action}
-    log(f"C3 A^(-1/2) b, {npole} Zolotarev poles on [{lo:.2e}, {1.05 * hi:.3f}] (rel. error {delta:.1e}): "
-        f"{wall:.3f} s, base {st[0]['iterations']} it; bounds {t_bounds:.3f} s")
+        "true_residual_max": max(v["true_residual"] for v in st), "pseudofermion_action": action,
+        "action_over_eta2_minus_1": action / eta2 - 1.0}
+    log(f"C3 action phi^+ A^(-1/2) phi, {npole} Zolotarev poles on [{lo:.2e}, {1.05 * hi:.3f}] (rel. error "
+        f"{delta:.1e}): {wall:.3f} s, base {st[0]['iterations']} it; S/|eta|^2 - 1 = {action / eta2 - 1:.1e}; "
+        f"bounds {t_bounds:.3f} s")
     p1 = out["plain_fp64_1rhs"]["seconds"]
     out["speedup_batched_per_rhs_vs_plain"] = round(p1 / out[f"batched_mixed_fp32_{n}rhs"]["seconds_per_rhs"], 3)
     out["speedup_multishift_per_shift_vs_plain"] = round(p1 / ms["seconds_per_rhs"], 3)

@@ -279,6 +279,29 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
                             double *shift, double *delta);
 
 /*
+ * Minimax relative rational approximation of x^power on [lmin, lmax], the
+ * coefficients of the RHMC rational functions for other roots than the
+ * square root (e.g. x^(1/4) for the two-flavour pseudofermion heat bath, and
+ * x^(-1/4), x^(1/8) for the strange quark; the paper's RHMC for 2+1 flavours,
+ * Sec. 2): on return
+ *     x^power ~ *alpha0 + sum_k alpha[k] / (x + shift[k]),  k < npole,
+ * with 0 < shift[0] < ... < shift[npole-1] and *delta (may be NULL) the
+ * largest relative error over the interval, at which the error equioscillates
+ * 2 npole + 2 times (Chebyshev's alternation theorem).  Remez exchange on the
+ * product form, started from Zolotarev's x^(-1/2) and continued along the
+ * power.  Every alpha[k] is positive for power < 0 and negative for
+ * power > 0.  Host only (no GPU).
+ *   0.05 <= |power| <= 0.95; 0 < lmin < lmax, lmax / lmin <= 1e14;
+ *   1 <= npole <= 64, and few enough poles that the x^(-1/2) error on the
+ *   same interval stays >= 1e-12 (HISQ_ERR_INVALID otherwise: the error
+ *   would drown in rounding)
+ * Returns HISQ_ERR_UNSUPPORTED if the exchange finds no equioscillating
+ * solution.
+ */
+int hisq_rational_remez(double power, double lmin, double lmax, int npole, double *alpha0,
+                        double *alpha, double *shift, double *delta);
+
+/*
  * Spectrum bounds of A for a rational approximation: *lmin = 4 m^2 (a lower
  * bound, since (D^+ D)_ee >= 0) and *lmax = the Rayleigh quotient of A after
  * `iters` FP64 power iterations from a fixed pseudo-random vector, an

@@ -12,9 +12,15 @@ What a rational-approximation solver must return, written from definitions:
   c_l = sn^2 / cn^2 (l K' / (2n + 1)), l = 1..2n, and
   r(x) = D prod_l (x + c_{2l}) / (x + c_{2l-1}) on [1, lmax/lmin], D centring
   the relative error; then partial fractions and rescaling to [lmin, lmax];
-* ``relative_error_extrema``: the local extrema of x^(1/2) r(x) - 1 on a fine
-  logarithmic grid, for the alternation test (a best approximation of type
-  (n, n) has 2n + 2 alternating extrema of equal size - Chebyshev).
+* ``relative_error_extrema``: the alternation set of the relative error
+  x^(-p) r(x) - 1 on a fine logarithmic grid (p = -1/2 by default), for the
+  alternation test: a best approximation of type (n, n) has 2n + 2
+  alternating extrema of equal size (Chebyshev).  This is the definition of
+  the minimax approximation and the pin of any construction of one, for every
+  power; the error is evaluated in extended precision, because for positive
+  powers the partial fractions cancel against alpha_0 near x = 0, and
+  neighbouring extrema of one sign (one flat peak split by rounding) count
+  once.
 Shares no code with the HIP library.
 """
 
@@ -95,11 +101,19 @@ def zolotarev_inv_sqrt(lmin, lmax, n):
     return D / s, res * s, p * lmin, float(delta)
 
 
-def relative_error_extrema(alpha0, alphas, shifts, lmin, lmax, npts=200001):
-    """Values of x^(1/2) r(x) - 1 at its local extrema on [lmin, lmax] (ends included)."""
-    x = np.exp(np.linspace(np.log(lmin), np.log(lmax), npts))
-    r = alpha0 + sum(a / (x + s) for a, s in zip(alphas, shifts))
-    e = np.sqrt(x) * r - 1.0
+def relative_error_extrema(alpha0, alphas, shifts, lmin, lmax, npts=200001, power=-0.5):
+    """Values of x^(-power) r(x) - 1 at its alternation points on [lmin, lmax] (ends included)."""
+    ld = np.longdouble
+    x = np.exp(np.linspace(np.log(ld(lmin)), np.log(ld(lmax)), npts, dtype=ld))
+    r = ld(alpha0) + sum(ld(a) / (x + ld(s)) for a, s in zip(alphas, shifts))
+    e = r * x ** ld(-power) - 1
     d = np.diff(e)
     k = np.where(np.sign(d[1:]) != np.sign(d[:-1]))[0] + 1
-    return np.concatenate([[e[0]], e[k], [e[-1]]])
+    ext = []
+    for v in np.concatenate([[e[0]], e[k], [e[-1]]]):
+        if ext and (ext[-1] > 0) == (v > 0):
+            if abs(v) > abs(ext[-1]):
+                ext[-1] = v
+        else:
+            ext.append(v)
+    return np.array(ext, dtype=np.float64)

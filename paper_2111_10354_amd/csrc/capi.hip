@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -304,6 +305,28 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
     return zolotarev_inv_sqrt(lmin, lmax, npole, alpha0, alpha, shift, delta);
+}
+
+int hisq_rational_remez(double power, double lmin, double lmax, int npole, double *alpha0, double *alpha,
+                        double *shift, double *delta) {
+    if (!std::isfinite(power) || !(std::fabs(power) >= 0.05 && std::fabs(power) <= 0.95))
+        return fail(HISQ_ERR_INVALID, "the power must satisfy 0.05 <= |p| <= 0.95");
+    if (!(lmin > 0.0) || !std::isfinite(lmin) || !std::isfinite(lmax) || !(lmax > lmin))
+        return fail(HISQ_ERR_INVALID, "need 0 < lmin < lmax, both finite");
+    if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
+    if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
+    if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
+    // below ~1e-12 relative error the alternation drowns in rounding: the
+    // x^(-1/2) optimum on the same interval measures how close that is
+    {
+        std::vector<double> za(npole), zs(npole);
+        double z0 = 0.0, zd = 0.0;
+        int rc = zolotarev_inv_sqrt(lmin, lmax, npole, &z0, za.data(), zs.data(), &zd);
+        if (rc) return rc;
+        if (zd < 1e-12)
+            return fail(HISQ_ERR_INVALID, "too many poles for this interval: the error would fall below 1e-12");
+    }
+    return remez_power(power, lmin, lmax, npole, alpha0, alpha, shift, delta);
 }
 
 int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, const double *alpha,

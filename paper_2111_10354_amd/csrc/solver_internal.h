@@ -184,6 +184,8 @@ int multishift_solve(hisq_gauge_s *g, double mass, int nshift, const double *shi
 // maximal relative error.  Host only.
 int zolotarev_inv_sqrt(double lmin, double lmax, int n, double *alpha0, double *alpha, double *shift,
                        double *delta);
+int remez_power(double power, double lmin, double lmax, int n, double *alpha0, double *alpha, double *shift,
+                double *delta);
 // out = alpha0 b + sum_k alpha[k] (A + shift[k])^(-1) b by one multi-shift CG.
 int rational_apply(hisq_gauge_s *g, double mass, double alpha0, int n, const double *alpha, const double *shift,
                    const double *b, double *out, const hisq_solver_params &prm, hisq_solver_stats *st,

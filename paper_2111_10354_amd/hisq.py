@@ -81,6 +81,7 @@ def _load():
         "hisq_rational_apply": (C.c_int, [vp, C.c_double, C.c_double, C.c_int, dp, dp, vp, vp,
                                           C.POINTER(SolverParams), C.POINTER(SolverStats), vp]),
         "hisq_zolotarev_inv_sqrt": (C.c_int, [C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
+        "hisq_rational_remez": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
         "hisq_spectral_bounds": (C.c_int, [vp, C.c_double, C.c_int, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -99,7 +100,7 @@ EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_c
            "hisq_autotune", "hisq_dslash_shape", "hisq_gauge_set_thin", "hisq_nn_create", "hisq_nn_destroy",
            "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
            "hisq_nn_train_step", "hisq_gauge_links_compressed", "hisq_rational_apply",
-           "hisq_zolotarev_inv_sqrt", "hisq_spectral_bounds")
+           "hisq_zolotarev_inv_sqrt", "hisq_rational_remez", "hisq_spectral_bounds")
 
 LINKS_FULL = 1 << 8  # hisq_gauge_create: store every link whole
 
@@ -262,6 +263,17 @@ def zolotarev_inv_sqrt(lmin: float, lmax: float, npole: int):
     a0, dl = C.c_double(0.0), C.c_double(0.0)
     al, sh = (C.c_double * npole)(), (C.c_double * npole)()
     _check(LIB.hisq_zolotarev_inv_sqrt(float(lmin), float(lmax), int(npole), C.byref(a0), al, sh, C.byref(dl)))
+    return a0.value, list(al), list(sh), dl.value
+
+
+def rational_remez(power: float, lmin: float, lmax: float, npole: int):
+    """(alpha0, alphas, shifts, delta): minimax relative approximation
+    x^power ~ alpha0 + sum_k alphas[k] / (x + shifts[k]) on [lmin, lmax] (host only)."""
+    a0, dl = C.c_double(0.0), C.c_double(0.0)
+    n = max(int(npole), 1)
+    al, sh = (C.c_double * n)(), (C.c_double * n)()
+    _check(LIB.hisq_rational_remez(float(power), float(lmin), float(lmax), int(npole), C.byref(a0), al, sh,
+                                   C.byref(dl)))
     return a0.value, list(al), list(sh), dl.value
 
 

@@ -1,5 +1,6 @@
-"""GPU rational functions of A (hisq_rational_apply, hisq_spectral_bounds)
-against the oracle: the exact dense A^(-1/2) b on 4^4 within the Zolotarev
+"""GPU rational functions of A (hisq_rational_apply, hisq_spectral_bounds,
+with hisq_zolotarev_inv_sqrt and hisq_rational_remez coefficients) against
+the oracle: the exact dense A^(-1/2) b on 4^4 within the Zolotarev
 error bound, and the oracle's partial-fraction sum (independent CGs per pole)
 on larger lattices within the solver tolerance.
 
@@ -99,4 +100,37 @@ def test_degenerate_and_invalid(cuda_device):
         hisq().rational_apply(g, 0.1, 0.0, [1.0], [0.1], bd, bd)
     with pytest.raises(hisq().HisqError):
         hisq().spectral_bounds(g, -0.1, 10)
+    g.close()
+
+
+@pytest.mark.parametrize("flavour", ["light", "strange"])
+def test_heatbath_action_identity(cuda_device, flavour):
+    """RHMC pseudofermions through the library, with Remez coefficients
+    (light: heat bath phi = A^(1/4) eta, action phi^+ A^(-1/2) phi; strange:
+    A^(1/8) and A^(-1/4)).  phi matches the oracle's partial-fraction
+    sum with the same coefficients, and the action returns |eta|^2 up to the
+    two approximation errors.  Tolerance of phi: the residues of a positive
+    power are negative and cancel against alpha0, so the solver error is
+    amplified by at most sum_k |alpha_k| / (lmin + sigma_k) / lmin^p <= alpha0 /
+    lmin^p, a factor ~20 here: at most 2e-9 for solves to 1e-10, under the
+    1e-8 asserted."""
+    dims = (8, 8, 8, 8)
+    F, L = fields(dims, cfg_id=0, eps=0.3)
+    g = make_gauge(dims, F, L)
+    mass = 0.05
+    lo, hi = hisq().spectral_bounds(g, mass, 200)
+    hi *= 1.05
+    ph, pa = (0.25, -0.5) if flavour == "light" else (0.125, -0.25)
+    h = hisq().rational_remez(ph, lo, hi, 12)
+    a = hisq().rational_remez(pa, lo, hi, 12)
+    eta = synth.gaussian_source(dims, 23, 1, parity=0)[0]
+    flush(f"heat bath {flavour} 8^4 [{lo:.2e}, {hi:.2f}] deltas {h[3]:.1e} {a[3]:.1e}")
+    rc, st, phi = run(g, dims, mass, h[0], h[1], h[2], eta)
+    assert rc == 0 and all(s["true_residual"] <= 1e-10 for s in st), st
+    want = R.rational_apply(dims, F, L, mass, h[0], h[1], h[2], eta, tol=1e-12)
+    assert np.linalg.norm(phi - want) / np.linalg.norm(want) < 1e-8
+    rc, st, psi = run(g, dims, mass, a[0], a[1], a[2], phi)
+    assert rc == 0, st
+    ratio = np.vdot(phi, psi).real / np.vdot(eta, eta).real
+    assert abs(ratio - 1) <= (1 + h[3]) ** 2 * (1 + a[3]) - 1 + 1e-8, (ratio, h[3], a[3])
     g.close()

@@ -11,6 +11,12 @@ Pins that do not reuse the construction being tested:
   sum must reproduce within the approximation's own error bound delta
   (|r(l) - l^(-1/2)| <= delta l^(-1/2) for every eigenvalue l in the interval);
 * one term with alpha = 1, sigma = 0 and alpha0 = 0 is A^(-1) b.
+
+The library's minimax approximations of other powers (Remez exchange) are
+pinned the same way: the alternation count and equal sizes on the oracle's
+grid, Zolotarev's closed form at p = -1/2 (the optimum is unique), the
+reciprocal and scaling symmetries, the exact dense A^p b on 4^4, and the
+heat-bath/action identity phi = A^(1/4) eta, phi^+ A^(-1/2) phi = |eta|^2.
 """
 
 import numpy as np
@@ -111,3 +117,111 @@ def test_golden_zolotarev_coefficients():
     assert a0 == pytest.approx(rec["alpha0"], rel=1e-9)
     assert np.allclose(al, rec["alpha"], rtol=1e-9) and np.allclose(sh, rec["shift"], rtol=1e-9)
     assert delta == pytest.approx(rec["delta"], rel=1e-5)
+
+
+# Minimax rational approximations of other powers (the library's Remez exchange).
+# The pin is Chebyshev's alternation theorem, the definition of the optimum:
+# 2n + 2 alternating extrema of one size, counted by the oracle on a fine grid.
+REMEZ_CASES = [(0.25, 1e-4, 40.0, 12), (-0.25, 1e-4, 40.0, 12), (0.125, 1e-5, 60.0, 14),
+               (-0.125, 1e-5, 60.0, 10), (0.375, 1e-4, 40.0, 8), (-0.75, 1e-4, 40.0, 16),
+               (0.75, 1e-4, 40.0, 12), (0.5, 1e-3, 10.0, 2), (-0.25, 1.0, 10.0, 1),
+               (0.05, 1e-4, 40.0, 16), (-0.9, 1e-4, 40.0, 16), (0.25, 1e-6, 100.0, 20),
+               (0.125, 1e-8, 64.0, 24)]
+
+
+@pytest.mark.parametrize("p,lmin,lmax,n", REMEZ_CASES)
+def test_library_remez_equioscillates(p, lmin, lmax, n):
+    from paper_2111_10354_amd import hisq
+    a0, al, sh, delta = hisq.rational_remez(p, lmin, lmax, n)
+    ex = R.relative_error_extrema(a0, al, sh, lmin, lmax, power=p)
+    assert len(ex) == 2 * n + 2
+    assert np.all(np.sign(ex[1:]) != np.sign(ex[:-1]))
+    mags = np.abs(ex)
+    assert mags.max() / mags.min() - 1 < 1e-4
+    assert abs(mags.max() / delta - 1) < 1e-4
+    # negative real poles: every shifted system is HPD; residues of one sign
+    sh, al = np.array(sh), np.array(al)
+    assert np.all(sh > 0) and np.all(np.diff(sh) > 0) and a0 > 0
+    assert np.all(np.sign(al) == -np.sign(p))
+
+
+@pytest.mark.parametrize("n,ratio", CASES + [(16, 1e10)])
+def test_library_remez_inverse_sqrt_is_zolotarev(n, ratio):
+    """p = -1/2: the best approximation is unique, so the exchange must land on
+    Zolotarev's closed form (the oracle's, from scipy's elliptic functions)."""
+    from paper_2111_10354_amd import hisq
+    lmin = 2e-3
+    a0, al, sh, delta = hisq.rational_remez(-0.5, lmin, lmin * ratio, n)
+    o0, oal, osh, od = R.zolotarev_inv_sqrt(lmin, lmin * ratio, n)
+    assert abs(a0 / o0 - 1) < 1e-6
+    assert np.max(np.abs(np.array(sh) / osh - 1)) < 1e-6
+    assert np.max(np.abs(np.array(al) / oal - 1)) < 1e-6
+    assert abs(delta / od - 1) < 1e-5
+
+
+@pytest.mark.parametrize("p", [0.125, 0.25, 0.375])
+def test_library_remez_reciprocal_and_scale(p):
+    """1/r approximates x^(-p) with error -e/(1+e): the optimal errors for p and
+    -p agree to O(delta^2).  x^p on [s a, s b] is s^p (x/s)^p: the shifts scale
+    by s, alpha0 by s^p, the residues by s^(p+1), the error not at all."""
+    from paper_2111_10354_amd import hisq
+    a = hisq.rational_remez(p, 1e-4, 40.0, 12)
+    m = hisq.rational_remez(-p, 1e-4, 40.0, 12)
+    assert abs(a[3] / m[3] - 1) < 1e-5 + 4 * a[3]
+    s = 100.0
+    b = hisq.rational_remez(p, 1e-4 * s, 40.0 * s, 12)
+    assert b[0] == pytest.approx(a[0] * s ** p, rel=1e-9)
+    assert np.allclose(b[2], np.array(a[2]) * s, rtol=1e-9)
+    assert np.allclose(b[1], np.array(a[1]) * s ** (p + 1), rtol=1e-9)
+    assert b[3] == pytest.approx(a[3], rel=1e-5)
+
+
+@pytest.mark.parametrize("p,n", [(0.25, 8), (-0.25, 8), (0.125, 6)])
+def test_remez_partial_fractions_match_dense_power(p, n):
+    """The library's coefficients applied by the oracle (one plain CG per pole)
+    reproduce the exact dense A^p b on 4^4 within the approximation's bound:
+    |r(l) - l^p| <= delta l^p for every eigenvalue l of A in the interval."""
+    from paper_2111_10354_amd import hisq
+    dims = (4, 4, 4, 4)
+    F, L = synth.hisq_links(dims, 99, 0.5)
+    mass = 0.1
+    b = synth.gaussian_source(dims, 21, 1, parity=0)[0]
+    exact, lo, hi = R.dense_power(dims, F, L, mass, b, p)
+    a0, al, sh, delta = hisq.rational_remez(p, lo, hi, n)
+    got = R.rational_apply(dims, F, L, mass, a0, al, sh, b)
+    err = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+    assert err <= delta * (1 + 1e-6) + 1e-10, (err, delta)
+
+
+def test_oracle_heatbath_action_identity():
+    """Rooted-staggered RHMC for two flavours: heat bath phi = A^(1/4) eta, action
+    S = phi^+ A^(-1/2) phi, so that S = |eta|^2 for every eta; with rational
+    approximations S / |eta|^2 - 1 is bounded by the errors of the two
+    approximations (|e1| <= d1 twice, |e2| <= d2 once)."""
+    from paper_2111_10354_amd import hisq
+    dims = (4, 4, 4, 4)
+    F, L = synth.hisq_links(dims, 99, 0.5)
+    mass = 0.1
+    eta = synth.gaussian_source(dims, 22, 1, parity=0)[0]
+    _, lo, hi = R.dense_power(dims, F, L, mass, eta, 1.0)
+    h = hisq.rational_remez(0.25, lo, hi, 6)
+    a = hisq.rational_remez(-0.5, lo, hi, 6)
+    phi = R.rational_apply(dims, F, L, mass, h[0], h[1], h[2], eta)
+    psi = R.rational_apply(dims, F, L, mass, a[0], a[1], a[2], phi)
+    ratio = np.vdot(phi, psi).real / np.vdot(eta, eta).real
+    bound = (1 + h[3]) ** 2 * (1 + a[3]) - 1
+    assert abs(ratio - 1) <= bound + 1e-10
+    assert abs(ratio - 1) > 1e-12        # the approximations are not exact
+
+
+@pytest.mark.parametrize("args", [(0.0, 1e-3, 1.0, 4), (0.97, 1e-3, 1.0, 4), (-1.0, 1e-3, 1.0, 4),
+                                  (0.25, 1.0, 0.5, 4), (0.25, 1e-3, 1.0, 0), (0.25, 1e-3, 1.0, 65),
+                                  (0.25, 1.0, 1.01, 6), (float("nan"), 1e-3, 1.0, 4),
+                                  (0.95, 1e-4, 40.0, 16)])
+def test_library_remez_rejects(args):
+    """Out of range, or more poles than double precision can resolve on the
+    interval (x^(1/4) with 6 poles on [1, 1.01]), or partial fractions that
+    lose the approximation to cancellation (x^0.95 over 5.6 decades)."""
+    from paper_2111_10354_amd import hisq
+    with pytest.raises(hisq.HisqError):
+        hisq.rational_remez(*args)
