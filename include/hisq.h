@@ -272,7 +272,8 @@ int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, c
  *     x^(-1/2) ~ *alpha0 + sum_k alpha[k] / (x + shift[k]),  k < npole,
  * with 0 < shift[0] < ... < shift[npole-1], every alpha[k] > 0, and *delta
  * (may be NULL) the largest relative error over the interval; the error
- * equioscillates 2 npole + 2 times.  Host only (no GPU).
+ * equioscillates 2 npole + 2 times (down to ~1e-13, where the rounding of
+ * the FP64 coefficients takes over).  Host only (no GPU).
  *   0 < lmin < lmax, lmax / lmin <= 1e14, 1 <= npole <= 64
  */
 int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0, double *alpha,
@@ -292,9 +293,9 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
  * power.  Every alpha[k] is positive for power < 0 and negative for
  * power > 0.  Host only (no GPU).
  *   0.05 <= |power| <= 0.95; 0 < lmin < lmax, lmax / lmin <= 1e14;
- *   1 <= npole <= 64, and few enough poles that the x^(-1/2) error on the
- *   same interval stays >= 1e-12 (HISQ_ERR_INVALID otherwise: the error
- *   would drown in rounding)
+ *   1 <= npole <= 64, and a pole count for which the x^(-1/2) error on the
+ *   same interval lies in [1e-12, 0.5] (HISQ_ERR_INVALID otherwise: below,
+ *   the error would drown in rounding; above, the approximation is useless)
  * Returns HISQ_ERR_UNSUPPORTED if the exchange finds no equioscillating
  * solution.
  */

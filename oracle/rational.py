@@ -13,7 +13,8 @@ What a rational-approximation solver must return, written from definitions:
   r(x) = D prod_l (x + c_{2l}) / (x + c_{2l-1}) on [1, lmax/lmin], D centring
   the relative error; then partial fractions and rescaling to [lmin, lmax];
 * ``relative_error_extrema``: the alternation set of the relative error
-  x^(-p) r(x) - 1 on a fine logarithmic grid (p = -1/2 by default), for the
+  x^(-p) r(x) - 1 on a fine logarithmic grid (p = -1/2 by default; each
+  interior extremum read off the parabola through its grid triple), for the
   alternation test: a best approximation of type (n, n) has 2n + 2
   alternating extrema of equal size (Chebyshev).  This is the definition of
   the minimax approximation and the pin of any construction of one, for every
@@ -68,9 +69,18 @@ def zolotarev_inv_sqrt(lmin, lmax, n):
     b = lmax / lmin
     m = 1.0 - 1.0 / b
     K = ellipk(m)
-    sn, cn, _, _ = ellipj(np.arange(1, 2 * n + 1) * K / (2 * n + 1), m)
-    c = sn ** 2 / cn ** 2
-    x = np.exp(np.linspace(0.0, np.log(b), 400 * n + 401))
+    # the lower half directly; the upper half from the quarter-period shift
+    # tn(K - v) tn(v) = 1 / sqrt(1 - m), i.e. c_l c_{2n+1-l} = 1 / (1 - m)
+    # (there cn is tiny and ellipj's cn has lost its relative accuracy).  The
+    # 1 - m that ellipj sees is the rounded one, so the mirror uses it too:
+    # every node then belongs to the same interval [1, 1 / (1 - m)], which
+    # differs from [1, b] by the rounding of m (~1e-16 b)
+    sn, cn, _, _ = ellipj(np.arange(1, n + 1) * K / (2 * n + 1), m)
+    lower = sn ** 2 / cn ** 2
+    c = np.concatenate([lower, (1.0 / (1.0 - m)) / lower[::-1]])
+    # fine enough that the parabola through a grid triple places each extremum
+    # value to ~1e-6 of the error itself (its error is cubic in the spacing)
+    x = np.exp(np.linspace(0.0, np.log(b), 8000 * n + 8001))
     f = np.sqrt(x) * _product(x, c, n)
     # refine every interior extremum by a parabola through the grid triple
     lo, hi = [f[0], f[-1]], [f[0], f[-1]]
@@ -94,9 +104,9 @@ def zolotarev_inv_sqrt(lmin, lmax, n):
     num = c[1::2]
     res = np.empty(n)
     for l in range(n):
-        v = D * np.prod(num - p[l])
+        # one ratio per factor: the separate products overflow for many poles
         others = np.delete(p, l)
-        res[l] = v / np.prod(others - p[l])
+        res[l] = D * (num[-1] - p[l]) * np.prod((num[:-1] - p[l]) / (others - p[l]))
     s = np.sqrt(lmin)
     return D / s, res * s, p * lmin, float(delta)
 
@@ -109,8 +119,14 @@ def relative_error_extrema(alpha0, alphas, shifts, lmin, lmax, npts=200001, powe
     e = r * x ** ld(-power) - 1
     d = np.diff(e)
     k = np.where(np.sign(d[1:]) != np.sign(d[:-1]))[0] + 1
+    # the peak value of the parabola through each grid triple: near the ends
+    # of the interval the extrema are sharp and the grid value under-reads them
+    em, e0, ep = e[k - 1], e[k], e[k + 1]
+    curv = ep - 2 * e0 + em
+    safe = np.where(curv != 0, curv, 1)
+    peak = np.where(curv != 0, e0 - (ep - em) ** 2 / (8 * safe), e0)
     ext = []
-    for v in np.concatenate([[e[0]], e[k], [e[-1]]]):
+    for v in np.concatenate([[e[0]], peak, [e[-1]]]):
         if ext and (ext[-1] > 0) == (v > 0):
             if abs(v) > abs(ext[-1]):
                 ext[-1] = v

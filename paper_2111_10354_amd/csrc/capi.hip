@@ -325,6 +325,8 @@ int hisq_rational_remez(double power, double lmin, double lmax, int npole, doubl
         if (rc) return rc;
         if (zd < 1e-12)
             return fail(HISQ_ERR_INVALID, "too many poles for this interval: the error would fall below 1e-12");
+        if (zd > 0.5)
+            return fail(HISQ_ERR_INVALID, "too few poles for this interval: the error would exceed 0.5");
     }
     return remez_power(power, lmin, lmax, npole, alpha0, alpha, shift, delta);
 }

@@ -28,41 +28,47 @@
 namespace hisq {
 
 // ------------------------------------------------------------------ elliptic functions (host)
+// In x87 extended precision: for large b = lmax / lmin the nodes below come
+// from cn ~ 1/sqrt(b) computed as cos(phi) near pi/2, whose relative error is
+// the working precision divided by cn; in double that limits the nodes to
+// ~1e-13 relative at b = 1e12, enough to break the equioscillation of an
+// approximation whose error is ~1e-11.
+//
 // Complete elliptic integral K(m) from the complementary parameter m1 = 1 - m
 // (accurate as m -> 1): K = pi / (2 AGM(1, sqrt(m1))).
-static double ellip_k_from_m1(double m1) {
-    double a = 1.0, b = std::sqrt(m1);
-    for (int i = 0; i < 64 && std::fabs(a - b) > 1e-17 * a; ++i) {
-        const double t = 0.5 * (a + b);
-        b = std::sqrt(a * b);
+static long double ellip_k_from_m1(long double m1) {
+    long double a = 1.0L, b = sqrtl(m1);
+    for (int i = 0; i < 64 && fabsl(a - b) > 1e-20L * a; ++i) {
+        const long double t = 0.5L * (a + b);
+        b = sqrtl(a * b);
         a = t;
     }
-    return M_PI / (2.0 * a);
+    return 3.14159265358979323846264338327950288L / (2.0L * a);
 }
 
 // Jacobi sn and cn of (u | m), m1 = 1 - m, by the descending Landen (AGM)
 // sequence: a_{n+1} = (a_n + b_n)/2, b_{n+1} = sqrt(a_n b_n),
 // c_{n+1} = (a_n - b_n)/2, then phi_N = 2^N a_N u and
 // phi_{n-1} = (phi_n + asin(c_n sin(phi_n) / a_n)) / 2; sn = sin phi_0.
-static void ellip_sn_cn(double u, double m1, double *sn, double *cn) {
+static void ellip_sn_cn(long double u, long double m1, long double *sn, long double *cn) {
     constexpr int NMAX = 48;
-    double a[NMAX + 1], c[NMAX + 1];
-    double an = 1.0, bn = std::sqrt(m1);
+    long double a[NMAX + 1], c[NMAX + 1];
+    long double an = 1.0L, bn = sqrtl(m1);
     a[0] = an;
-    c[0] = std::sqrt(1.0 - m1);
+    c[0] = sqrtl(1.0L - m1);
     int n = 0;
-    while (n < NMAX && std::fabs(c[n]) > 1e-17 * a[n]) {
-        const double a1 = 0.5 * (an + bn), b1 = std::sqrt(an * bn), c1 = 0.5 * (an - bn);
+    while (n < NMAX && fabsl(c[n]) > 1e-20L * a[n]) {
+        const long double a1 = 0.5L * (an + bn), b1 = sqrtl(an * bn), c1 = 0.5L * (an - bn);
         an = a1;
         bn = b1;
         ++n;
         a[n] = an;
         c[n] = c1;
     }
-    double phi = std::ldexp(a[n] * u, n);
-    for (int k = n; k > 0; --k) phi = 0.5 * (phi + std::asin(c[k] * std::sin(phi) / a[k]));
-    *sn = std::sin(phi);
-    *cn = std::cos(phi);
+    long double phi = ldexpl(a[n] * u, n);
+    for (int k = n; k > 0; --k) phi = 0.5L * (phi + asinl(c[k] * sinl(phi) / a[k]));
+    *sn = sinl(phi);
+    *cn = cosl(phi);
 }
 
 // sqrt(x) prod_l (x + c_{2l}) / (x + c_{2l-1}) (c 0-based: c[2l+1] / c[2l])
@@ -97,14 +103,19 @@ static double zolo_extremum(double lo, double hi, const std::vector<double> &c, 
 }
 
 // c_l = sn^2 / cn^2 (l K' / (2n + 1); k'), l = 1 .. 2n, for the interval [1, b]
+// Only l <= n is evaluated: for u near K' cn is tiny and loses its relative
+// accuracy.  The upper half follows from the quarter-period shift
+// tn(K' - v) = 1 / (sqrt(1 - k'^2) tn(v)), i.e. c_l c_{2n+1-l} = b.
 static std::vector<double> zolotarev_nodes(double b, int n) {
-    const double m1 = 1.0 / b;  // 1 - k'^2
-    const double K = ellip_k_from_m1(m1);
+    const long double m1 = 1.0L / (long double)b;  // 1 - k'^2
+    const long double K = ellip_k_from_m1(m1);
     std::vector<double> c(2 * n);
-    for (int l = 1; l <= 2 * n; ++l) {
-        double sn, cn;
+    for (int l = 1; l <= n; ++l) {
+        long double sn, cn;
         ellip_sn_cn(l * K / (2 * n + 1), m1, &sn, &cn);
-        c[l - 1] = (sn * sn) / (cn * cn);
+        const long double t = (sn * sn) / (cn * cn);
+        c[l - 1] = (double)t;
+        c[2 * n - l] = (double)((long double)b / t);
     }
     return c;
 }

@@ -137,8 +137,13 @@ def test_library_remez_equioscillates(p, lmin, lmax, n):
     assert len(ex) == 2 * n + 2
     assert np.all(np.sign(ex[1:]) != np.sign(ex[:-1]))
     mags = np.abs(ex)
-    assert mags.max() / mags.min() - 1 < 1e-4
-    assert abs(mags.max() / delta - 1) < 1e-4
+    # the FP64 coefficients of a positive power cancel against alpha0 near
+    # lmin (r(0) ~ 0): their rounding enters the relative error amplified by
+    # (|alpha0| + sum |alpha_k| / (lmin + sigma_k)) / r(lmin)
+    amp = (abs(a0) + sum(abs(a) / (lmin + s) for a, s in zip(al, sh))) / lmin ** p
+    tol = 1e-4 + 64 * np.finfo(np.float64).eps * amp / delta
+    assert mags.max() / mags.min() - 1 < tol
+    assert abs(mags.max() / delta - 1) < tol
     # negative real poles: every shifted system is HPD; residues of one sign
     sh, al = np.array(sh), np.array(al)
     assert np.all(sh > 0) and np.all(np.diff(sh) > 0) and a0 > 0
@@ -174,6 +179,41 @@ def test_library_remez_reciprocal_and_scale(p):
     assert np.allclose(b[2], np.array(a[2]) * s, rtol=1e-9)
     assert np.allclose(b[1], np.array(a[1]) * s ** (p + 1), rtol=1e-9)
     assert b[3] == pytest.approx(a[3], rel=1e-5)
+
+
+@pytest.mark.parametrize("n,ratio", [(24, 1e9), (32, 1e9), (32, 1e12), (40, 1e14)])
+def test_library_zolotarev_equioscillates_at_large_ratios(n, ratio):
+    """Many poles over many decades: the nodes near the top of the interval
+    come from a tiny cn, so they are mirrored from the lower half
+    (c_l c_{2n+1-l} = b).  The definition then holds down to the accuracy of
+    the lower nodes (~1e-12 relative at b = 1e14: the asin steps of the
+    descending Landen sequence amplify rounding as m -> 1), i.e. an error
+    curve uneven by ~1e-12 absolute, which the tolerance allows."""
+    from paper_2111_10354_amd import hisq
+    lmin = 1e-3
+    a0, al, sh, delta = hisq.zolotarev_inv_sqrt(lmin, lmin * ratio, n)
+    ex = R.relative_error_extrema(a0, al, sh, lmin, lmin * ratio, npts=400001)
+    assert len(ex) == 2 * n + 2
+    assert np.all(np.sign(ex[1:]) != np.sign(ex[:-1]))
+    mags = np.abs(ex)
+    tol = 1e-4 + 2e-12 / delta
+    assert mags.max() / mags.min() - 1 < tol
+    assert abs(mags.max() / delta - 1) < tol
+
+
+@pytest.mark.parametrize("p,n,ratio", [(-0.25, 24, 1e9), (0.125, 32, 1e12), (-0.125, 40, 1e14)])
+def test_library_remez_equioscillates_at_large_ratios(p, n, ratio):
+    from paper_2111_10354_amd import hisq
+    lmin = 1e-3
+    a0, al, sh, delta = hisq.rational_remez(p, lmin, lmin * ratio, n)
+    ex = R.relative_error_extrema(a0, al, sh, lmin, lmin * ratio, npts=400001, power=p)
+    assert len(ex) == 2 * n + 2
+    assert np.all(np.sign(ex[1:]) != np.sign(ex[:-1]))
+    mags = np.abs(ex)
+    amp = (abs(a0) + sum(abs(a) / (lmin + s) for a, s in zip(al, sh))) / lmin ** p
+    tol = 1e-4 + 2e-12 / delta + 64 * np.finfo(np.float64).eps * amp / delta
+    assert mags.max() / mags.min() - 1 < tol
+    assert abs(mags.max() / delta - 1) < tol
 
 
 @pytest.mark.parametrize("p,n", [(0.25, 8), (-0.25, 8), (0.125, 6)])
@@ -217,10 +257,11 @@ def test_oracle_heatbath_action_identity():
 @pytest.mark.parametrize("args", [(0.0, 1e-3, 1.0, 4), (0.97, 1e-3, 1.0, 4), (-1.0, 1e-3, 1.0, 4),
                                   (0.25, 1.0, 0.5, 4), (0.25, 1e-3, 1.0, 0), (0.25, 1e-3, 1.0, 65),
                                   (0.25, 1.0, 1.01, 6), (float("nan"), 1e-3, 1.0, 4),
-                                  (0.95, 1e-4, 40.0, 16)])
+                                  (0.95, 1e-4, 40.0, 16), (-0.25, 1e-6, 1.0, 1)])
 def test_library_remez_rejects(args):
     """Out of range, or more poles than double precision can resolve on the
-    interval (x^(1/4) with 6 poles on [1, 1.01]), or partial fractions that
+    interval (x^(1/4) with 6 poles on [1, 1.01]), or too few to be of any use
+    (one pole over six decades: error above 0.5), or partial fractions that
     lose the approximation to cancellation (x^0.95 over 5.6 decades)."""
     from paper_2111_10354_amd import hisq
     with pytest.raises(hisq.HisqError):
