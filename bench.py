@@ -48,10 +48,10 @@ def encode(cb, prec):
     return layout.encode(cb, prec)
 
 
-def counter_traffic(dims, compressed):
+def counter_traffic(dims, compressed, shape):
     """HBM bytes per launch of the headline kernel from the committed rocprofv3
-    counter summary, or None if the kernel sources or the link layout changed
-    since it was taken."""
+    counter summary, or None if the kernel sources, the link layout or the
+    launch shape (RHS tile, block, tile order) changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"dslash_fp32_{'x'.join(map(str, dims))}.traffic.json")
     if not os.path.exists(path):
@@ -62,6 +62,8 @@ def counter_traffic(dims, compressed):
     if hashlib.sha256(src).hexdigest() != rec.get("kernel_sources_sha256"):
         return None
     if bool(rec.get("long_links_compressed", False)) != bool(compressed):
+        return None
+    if rec.get("launch_shape") != [int(v) for v in shape]:
         return None
     return rec["traffic_bytes_per_launch"] / 1e9  # GB, like `achieved`
 
@@ -331,7 +333,7 @@ def main():
                    "dims": list(dims), "sites_per_parity": vh, "bytes_per_step": algo_bytes("fp32"),
                    "flop_per_site": FLOP_PER_SITE},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dims, False),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dims, False, shape),
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "cpu_baseline": cpu,
         "parity_rel_l2_vs_oracle": perr,
