@@ -22,6 +22,11 @@ What a rational-approximation solver must return, written from definitions:
   powers the partial fractions cancel against alpha_0 near x = 0, and
   neighbouring extrema of one sign (one flat peak split by rounding) count
   once.
+* ``minimax_bruteforce``: the definition minimised directly for tiny pole
+  counts - the largest relative error of c prod (x + z_i) / (x + q_i) against
+  x^p over a logarithmic grid, minimised over (log c, log z, log q) by
+  repeated Nelder-Mead; for one pole (three parameters) this finds the optimum,
+  for more it gives an upper bound on the optimal error.
 Shares no code with the HIP library.
 """
 
@@ -133,3 +138,27 @@ def relative_error_extrema(alpha0, alphas, shifts, lmin, lmax, npts=200001, powe
         else:
             ext.append(v)
     return np.array(ext, dtype=np.float64)
+
+
+def minimax_bruteforce(p, lmin, lmax, n, npts=4001, restarts=6):
+    """(delta, shifts): the smallest max relative error of a type (n, n)
+    rational approximation of x^p on [lmin, lmax] that direct minimisation
+    finds, and its poles -q_i (as shifts q_i, ascending)."""
+    from scipy.optimize import minimize
+    x = np.exp(np.linspace(np.log(lmin), np.log(lmax), npts))
+    lx = np.log(x)
+
+    def max_err(th):
+        lc, lz, lq = th[0], th[1:n + 1], th[n + 1:]
+        lr = lc + np.sum(np.log(x[:, None] + np.exp(lz)[None, :]) - np.log(x[:, None] + np.exp(lq)[None, :]), axis=1)
+        return float(np.max(np.abs(np.expm1(lr - p * lx))))
+
+    # start: zeros and poles interlaced, evenly spread in log x
+    t = np.linspace(np.log(lmin), np.log(lmax), 2 * n + 2)[1:-1]
+    lq0, lz0 = (t[0::2], t[1::2]) if p < 0 else (t[1::2], t[0::2])
+    lc0 = np.mean(p * lx - np.sum(np.log(x[:, None] + np.exp(lz0)) - np.log(x[:, None] + np.exp(lq0)), axis=1))
+    th = np.concatenate([[lc0], lz0, lq0])
+    for _ in range(restarts):
+        th = minimize(max_err, th, method="Nelder-Mead",
+                      options={"xatol": 1e-12, "fatol": 1e-15, "maxiter": 20000, "maxfev": 40000}).x
+    return max_err(th), np.sort(np.exp(th[n + 1:]))

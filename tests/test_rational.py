@@ -181,6 +181,29 @@ def test_library_remez_reciprocal_and_scale(p):
     assert b[3] == pytest.approx(a[3], rel=1e-5)
 
 
+@pytest.mark.parametrize("p,lmin,lmax", [(0.25, 1e-2, 1.0), (-0.25, 1e-3, 1.0), (0.125, 1.0, 100.0),
+                                           (-0.75, 1e-2, 1.0)])
+def test_library_remez_one_pole_is_the_bruteforce_optimum(p, lmin, lmax):
+    """One pole: the optimum of the three-parameter problem, found by direct
+    minimisation of the largest error on a grid (no exchange, no alternation),
+    is the library's."""
+    from paper_2111_10354_amd import hisq
+    a0, al, sh, delta = hisq.rational_remez(p, lmin, lmax, 1)
+    bd, bq = R.minimax_bruteforce(p, lmin, lmax, 1)
+    assert abs(bd / delta - 1) < 1e-5
+    assert abs(bq[0] / sh[0] - 1) < 1e-4
+
+
+@pytest.mark.parametrize("p,lmin,lmax", [(0.125, 1.0, 100.0), (-0.5, 1e-2, 1.0), (0.375, 1e-2, 1.0)])
+def test_library_remez_two_poles_beat_bruteforce(p, lmin, lmax):
+    """Two poles: whatever direct minimisation finds is an approximation of the
+    same type, so its error bounds the optimum from above."""
+    from paper_2111_10354_amd import hisq
+    delta = hisq.rational_remez(p, lmin, lmax, 2)[3]
+    bd, _ = R.minimax_bruteforce(p, lmin, lmax, 2)
+    assert delta <= bd * (1 + 1e-9)
+
+
 @pytest.mark.parametrize("n,ratio", [(24, 1e9), (32, 1e9), (32, 1e12), (40, 1e14)])
 def test_library_zolotarev_equioscillates_at_large_ratios(n, ratio):
     """Many poles over many decades: the nodes near the top of the interval
