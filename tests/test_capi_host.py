@@ -128,3 +128,24 @@ def test_no_bit_cast_of_vector_elements_in_device_code():
             if pat.search(line):
                 bad.append(f"{os.path.basename(path)}:{i}: {line.strip()}")
     assert not bad, bad
+
+
+def test_bench_traffic_is_keyed_on_sources_layout_and_shape():
+    """The counter traffic that bench.py reports belongs to one kernel source
+    hash, link layout and launch shape; any other combination reports None."""
+    import json
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "dslash_fp32_96x96x96x24.traffic.json")))
+    dims = (96, 96, 96, 24)
+    shape = tuple(rec["launch_shape"])
+    got = bench.counter_traffic(dims, rec["long_links_compressed"], shape)
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2111_10354_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, n), "rb").read() for n in ("dslash.hip", "hisq_internal.h", "pack.hip"))
+    if hashlib.sha256(src).hexdigest() == rec["kernel_sources_sha256"]:
+        assert got == pytest.approx(rec["traffic_bytes_per_launch"] / 1e9)
+    else:  # kernel changed since the counters were taken: no traffic claimed
+        assert got is None
+    assert bench.counter_traffic(dims, rec["long_links_compressed"], (shape[0], shape[1], shape[2] + 1)) is None
+    assert bench.counter_traffic(dims, not rec["long_links_compressed"], shape) is None
+    assert bench.counter_traffic((48, 48, 48, 12), False, shape) is None
