@@ -289,3 +289,32 @@ def test_library_remez_rejects(args):
     from paper_2111_10354_amd import hisq
     with pytest.raises(hisq.HisqError):
         hisq.rational_remez(*args)
+
+
+def test_library_remez_random_cases_equioscillate():
+    """Random powers, intervals and pole counts (deterministic draw): every
+    accepted request returns an approximation that meets the definition on the
+    oracle's grid; refused requests are the documented ones."""
+    from hypothesis import HealthCheck, given, settings, strategies as st
+    from paper_2111_10354_amd import hisq
+
+    @settings(max_examples=30, deadline=None, derandomize=True, suppress_health_check=list(HealthCheck))
+    @given(p=st.one_of(st.floats(-0.9, -0.05), st.floats(0.05, 0.6)), lratio=st.floats(0.5, 8.0),
+           n=st.integers(1, 12))
+    def check(p, lratio, n):
+        lmin, lmax = 1e-3, 1e-3 * 10 ** lratio
+        try:
+            a0, al, sh, delta = hisq.rational_remez(p, lmin, lmax, n)
+        except hisq.HisqError as e:
+            assert any(w in str(e) for w in ("too many poles", "too few poles", "cancellation")), str(e)
+            return
+        ex = R.relative_error_extrema(a0, al, sh, lmin, lmax, power=p)
+        assert len(ex) == 2 * n + 2, (p, lratio, n)
+        assert np.all(np.sign(ex[1:]) != np.sign(ex[:-1]))
+        mags = np.abs(ex)
+        amp = (abs(a0) + sum(abs(a) / (lmin + s) for a, s in zip(al, sh))) / lmin ** p
+        tol = 1e-4 + 2e-12 / delta + 64 * np.finfo(np.float64).eps * amp / delta
+        assert mags.max() / mags.min() - 1 < tol, (p, lratio, n, mags.max() / mags.min() - 1)
+        assert abs(mags.max() / delta - 1) < tol
+
+    check()
