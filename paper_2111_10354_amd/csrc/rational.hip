@@ -309,7 +309,7 @@ bool solve_reference(const std::vector<double> &t, double p, ProdForm &r, double
                 trial.lq[i] = r.lq[i] + lam * d[1 + n + i];
             }
             Et = E + lam * d[m - 1];
-            if (!(std::fabs(Et) < 0.5)) continue;
+            if (!(std::fabs(Et) < 0.9)) continue;
             trial.sync();
             rt = reference_residual(t, p, trial, Et, g);
             if (rt < res) {

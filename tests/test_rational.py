@@ -126,7 +126,7 @@ REMEZ_CASES = [(0.25, 1e-4, 40.0, 12), (-0.25, 1e-4, 40.0, 12), (0.125, 1e-5, 60
                (-0.125, 1e-5, 60.0, 10), (0.375, 1e-4, 40.0, 8), (-0.75, 1e-4, 40.0, 16),
                (0.75, 1e-4, 40.0, 12), (0.5, 1e-3, 10.0, 2), (-0.25, 1.0, 10.0, 1),
                (0.05, 1e-4, 40.0, 16), (-0.9, 1e-4, 40.0, 16), (0.25, 1e-6, 100.0, 20),
-               (0.125, 1e-8, 64.0, 24)]
+               (0.125, 1e-8, 64.0, 24), (0.55, 1e-3, 100.0, 1)]
 
 
 @pytest.mark.parametrize("p,lmin,lmax,n", REMEZ_CASES)
