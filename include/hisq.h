@@ -274,7 +274,8 @@ int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, c
  * (may be NULL) the largest relative error over the interval; the error
  * equioscillates 2 npole + 2 times (down to ~1e-13, where the rounding of
  * the FP64 coefficients takes over).  Host only (no GPU).
- *   0 < lmin < lmax, lmax / lmin <= 1e14, 1 <= npole <= 64
+ *   0 < lmin < lmax, lmax / lmin <= 1e14, 1 <= npole <= 64; alpha and shift
+ *   are host double[npole] arrays that must not overlap
  */
 int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0, double *alpha,
                             double *shift, double *delta);
@@ -292,6 +293,7 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
  * product form, started from Zolotarev's x^(-1/2) and continued along the
  * power.  Every alpha[k] is positive for power < 0 and negative for
  * power > 0.  Host only (no GPU).
+ *   alpha, shift host double[npole] arrays that must not overlap;
  *   0.05 <= |power| <= 0.95; 0 < lmin < lmax, lmax / lmin <= 1e14;
  *   1 <= npole <= 64, and a pole count for which the x^(-1/2) error on the
  *   same interval lies in [1e-12, 0.5] (HISQ_ERR_INVALID otherwise: below,

@@ -304,6 +304,7 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
     if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
+    if (alpha < shift + npole && shift < alpha + npole) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
     return zolotarev_inv_sqrt(lmin, lmax, npole, alpha0, alpha, shift, delta);
 }
 
@@ -316,6 +317,7 @@ int hisq_rational_remez(double power, double lmin, double lmax, int npole, doubl
     if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
+    if (alpha < shift + npole && shift < alpha + npole) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
     // below ~1e-12 relative error the alternation drowns in rounding: the
     // x^(-1/2) optimum on the same interval measures how close that is
     {

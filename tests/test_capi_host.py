@@ -78,11 +78,14 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.hisq_cg_solve(None, 0.1, 1, dummy, dummy, None, None, None) == hisq.ERR_INVALID
     assert L.hisq_precond_apply(None, None, dummy, dummy, None) == hisq.ERR_INVALID
     a0 = C.c_double()
-    arr = (C.c_double * 4)()
-    assert L.hisq_rational_remez(0.25, 1e-3, 1.0, 4, None, arr, arr, None) == hisq.ERR_INVALID
-    assert L.hisq_rational_remez(0.0, 1e-3, 1.0, 4, C.byref(a0), arr, arr, None) == hisq.ERR_INVALID
-    assert L.hisq_zolotarev_inv_sqrt(1e-3, 1.0, 4, C.byref(a0), None, arr, None) == hisq.ERR_INVALID
-    assert L.hisq_rational_remez(0.25, 1e-3, 1.0, 4, C.byref(a0), arr, arr, None) == hisq.OK
+    al, sh = (C.c_double * 4)(), (C.c_double * 4)()
+    assert L.hisq_rational_remez(0.25, 1e-3, 1.0, 4, None, al, sh, None) == hisq.ERR_INVALID
+    assert L.hisq_rational_remez(0.0, 1e-3, 1.0, 4, C.byref(a0), al, sh, None) == hisq.ERR_INVALID
+    assert L.hisq_rational_remez(0.25, 1e-3, 1.0, 4, C.byref(a0), al, al, None) == hisq.ERR_INVALID
+    assert "overlap" in hisq.last_error()
+    assert L.hisq_zolotarev_inv_sqrt(1e-3, 1.0, 4, C.byref(a0), None, sh, None) == hisq.ERR_INVALID
+    assert L.hisq_zolotarev_inv_sqrt(1e-3, 1.0, 4, C.byref(a0), al, al, None) == hisq.ERR_INVALID
+    assert L.hisq_rational_remez(0.25, 1e-3, 1.0, 4, C.byref(a0), al, sh, None) == hisq.OK
     assert L.hisq_gauge_destroy(None) == hisq.OK
 
 
