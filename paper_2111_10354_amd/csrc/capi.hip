@@ -3,6 +3,7 @@
 // GPU; invalid arguments return HISQ_ERR_INVALID without any HIP call.
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -297,6 +298,13 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }
 
+// two host arrays of n doubles share memory (compared as addresses, since
+// the pointers need not belong to one array)
+static bool ranges_overlap(const double *a, const double *b, int n) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b, len = sizeof(double) * (uintptr_t)n;
+    return pa < pb + len && pb < pa + len;
+}
+
 int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0, double *alpha, double *shift,
                             double *delta) {
     if (!(lmin > 0.0) || !std::isfinite(lmin) || !std::isfinite(lmax) || !(lmax > lmin))
@@ -304,7 +312,7 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
     if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
-    if (alpha < shift + npole && shift < alpha + npole) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
+    if (ranges_overlap(alpha, shift, npole)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
     return zolotarev_inv_sqrt(lmin, lmax, npole, alpha0, alpha, shift, delta);
 }
 
@@ -317,7 +325,7 @@ int hisq_rational_remez(double power, double lmin, double lmax, int npole, doubl
     if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
-    if (alpha < shift + npole && shift < alpha + npole) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
+    if (ranges_overlap(alpha, shift, npole)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
     // below ~1e-12 relative error the alternation drowns in rounding: the
     // x^(-1/2) optimum on the same interval measures how close that is
     {
