@@ -12,7 +12,9 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hisq_oracle.c")
 
-# (name, text replaced, replacement); the first occurrence is oracle_dslash's
+# (name, text replaced, replacement[, function]): the first occurrence in the
+# file (the operator helpers, then oracle_dslash), or the first one after the
+# named function's definition
 MUTATIONS = [
     ("backward hop sign", "add_mdag_v(acc, link_at(F, b1, mu), in + b1 * 3, -1.0);",
      "add_mdag_v(acc, link_at(F, b1, mu), in + b1 * 3, +1.0);"),
@@ -28,7 +30,21 @@ MUTATIONS = [
      "const double diag = 2.0 * mass * mass + sigma;"),
     ("staggered phase of the wrong direction", "for (int nu = 0; nu < mu; ++nu) e += c[nu];",
      "for (int nu = 0; nu <= mu; ++nu) e += c[nu];"),
+    # the sampled-site evaluation that judges the full-size GPU parity
+    ("sites: backward Naik link read at the output site", "add_mdag_v(acc, link_at(N, b3, mu), in + b3 * 3, -1.0);",
+     "add_mdag_v(acc, link_at(N, s, mu), in + b3 * 3, -1.0);", "oracle_dslash_sites"),
+    ("sites: forward fat hop of three sites", "add_mv(acc, link_at(F, s, mu), in + f1 * 3, +1.0);",
+     "add_mv(acc, link_at(F, s, mu), in + f3 * 3, +1.0);", "oracle_dslash_sites"),
+    ("sites: backward fat term dropped", "add_mdag_v(acc, link_at(F, b1, mu), in + b1 * 3, -1.0);", "",
+     "oracle_dslash_sites"),
 ]
+
+
+def mutate(src, old, new, function=None):
+    """src with the first `old` (after the definition of `function`) replaced by `new`."""
+    start = src.index(f"void {function}(") if function else 0
+    at = src.index(old, start)
+    return src[:at] + new + src[at + len(old):]
 
 
 def run_pins(tmp_path, source):
@@ -50,10 +66,10 @@ def test_unchanged_copy_passes(tmp_path):
     assert r.returncode == 0, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+@pytest.mark.parametrize("mut", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, mut):
+    name, old, new = mut[:3]
     src = open(SRC).read()
-    assert old in src, name
-    r = run_pins(tmp_path, src.replace(old, new, 1))
+    r = run_pins(tmp_path, mutate(src, old, new, *mut[3:]))
     # a failed pin, not a crash or an import error
     assert r.returncode == 1 and " failed" in r.stdout, f"no pin caught: {name}\n{r.stdout[-2000:]}"

@@ -56,6 +56,54 @@ def test_free_field_eigenvalue_closed_form_values():
     assert abs((val - p) / p ** 5 + 3 / 40) < 1e-3
 
 
+def _free_dslash_closed_form(dims, c1, c3, colour, p):
+    """(D v)(x) for a plane wave v = e^{ip.x} colour on the other parity and free
+    folded links F = c1 eta bc, L = c3 eta bc: a hop of +-1 or +-3 sites along mu
+    multiplies by e^{+-ip_mu} or e^{+-3ip_mu} (with an antiperiodic time direction
+    the boundary sign cancels against the half-odd momentum), so
+    (D v)(x) = 2i sum_mu eta_mu(x) (c1 sin p_mu + c3 sin 3p_mu) e^{ip.x} colour."""
+    coef = 2j * (c1 * np.sin(p) + c3 * np.sin(3 * p))
+    phase = np.exp(1j * (synth.site_coords(dims) @ p))
+    return (synth.staggered_eta(dims) @ coef)[:, None] * phase[:, None] * np.asarray(colour)[None, :]
+
+
+@pytest.mark.parametrize("dims,apbc", [((4, 4, 4, 4), False), ((6, 4, 4, 10), True), ((8, 6, 4, 10), False)])
+@pytest.mark.parametrize("c1,c3", COEFFS)
+def test_free_field_dslash_closed_form_at_every_site(dims, apbc, c1, c3):
+    """The Dslash itself (not only A) on free-field plane waves, against the
+    closed form at every output site of both parities - through the whole-lattice
+    operator and through the sampled-site evaluation used at large sizes."""
+    F, L = synth.free_links(dims, c1, c3, antiperiodic_t=apbc)
+    rng = np.random.default_rng(11)
+    par = synth.site_parity(dims)
+    for out_par in (0, 1):
+        n = [int(rng.integers(0, d)) for d in dims]
+        colour = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        v, p = synth.plane_wave(dims, n, colour, parity=1 - out_par, antiperiodic_t=apbc)
+        want = _free_dslash_closed_form(dims, c1, c3, colour, p)
+        want[par != out_par] = 0
+        got = oracle.dslash(dims, F, L, v, out_par)
+        assert _rel(got, want) < 1e-13
+        sites = np.nonzero(par == out_par)[0]
+        got_s = oracle.dslash_sites(dims, F, L, v, sites)
+        assert _rel(got_s, want[sites]) < 1e-13
+
+
+@pytest.mark.parametrize("dims,apbc", [((4, 4, 4, 4), False), ((6, 4, 4, 10), True), ((8, 6, 4, 10), False)])
+def test_dslash_sites_equals_dslash_everywhere(dims, apbc):
+    """The sampled-site evaluation (which judges the full-size GPU parity) gives
+    the whole-lattice operator's value at every site, of either parity, on random
+    fields, in any order of the sites."""
+    F, L = synth.hisq_links(dims, 99, 0.5, antiperiodic_t=apbc)
+    for out_par in (0, 1):
+        chi = synth.gaussian_source(dims, 99, 1, parity=1 - out_par, index0=3)[0]
+        full = oracle.dslash(dims, F, L, chi, out_par)
+        sites = np.random.default_rng(out_par).permutation(synth.volume(dims))
+        got = oracle.dslash_sites(dims, F, L, chi, sites)
+        # bit for bit: the same sum in the same order (zero on the input's parity)
+        assert np.array_equal(got, full[sites])
+
+
 @pytest.mark.parametrize("dims,apbc", [((4, 4, 4, 4), False), ((6, 4, 4, 8), True)])
 def test_anti_hermiticity_random_fields(dims, apbc):
     F, L = synth.hisq_links(dims, 99, 0.5, antiperiodic_t=apbc)

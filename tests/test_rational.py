@@ -194,14 +194,30 @@ def test_library_remez_one_pole_is_the_bruteforce_optimum(p, lmin, lmax):
     assert abs(bq[0] / sh[0] - 1) < 1e-4
 
 
+@pytest.mark.parametrize("n", [1, 2])
+@pytest.mark.parametrize("lmin,lmax", [(1e-2, 1.0), (1e-3, 10.0), (1.0, 100.0)])
+def test_oracle_bruteforce_finds_zolotarev_optimum(n, lmin, lmax):
+    """Pin of the brute-force minimisation (oracle only): at p = -1/2 the best
+    relative approximation is unique and Zolotarev's closed form gives it, so
+    direct minimisation of the largest error must land on its error and its
+    poles."""
+    bd, bq = R.minimax_bruteforce(-0.5, lmin, lmax, n)
+    _, _, sh, delta = R.zolotarev_inv_sqrt(lmin, lmax, n)
+    assert abs(bd / delta - 1) < 2e-6
+    assert np.max(np.abs(bq / np.array(sh) - 1)) < 1e-6
+
+
 @pytest.mark.parametrize("p,lmin,lmax", [(0.125, 1.0, 100.0), (-0.5, 1e-2, 1.0), (0.375, 1e-2, 1.0)])
-def test_library_remez_two_poles_beat_bruteforce(p, lmin, lmax):
-    """Two poles: whatever direct minimisation finds is an approximation of the
-    same type, so its error bounds the optimum from above."""
+def test_library_remez_two_poles_is_the_bruteforce_optimum(p, lmin, lmax):
+    """Two poles: direct minimisation of the largest error (five parameters, no
+    exchange, no alternation) reaches the library's error and poles, and never
+    goes below it (it is an approximation of the same type)."""
     from paper_2111_10354_amd import hisq
-    delta = hisq.rational_remez(p, lmin, lmax, 2)[3]
-    bd, _ = R.minimax_bruteforce(p, lmin, lmax, 2)
-    assert delta <= bd * (1 + 1e-9)
+    _, _, sh, delta = hisq.rational_remez(p, lmin, lmax, 2)
+    bd, bq = R.minimax_bruteforce(p, lmin, lmax, 2)
+    assert delta <= bd * (1 + 1e-6)
+    assert bd <= delta * (1 + 1e-4)
+    assert np.max(np.abs(bq / np.array(sh) - 1)) < 1e-3
 
 
 @pytest.mark.parametrize("n,ratio", [(24, 1e9), (32, 1e9), (32, 1e12), (40, 1e14)])
