@@ -148,8 +148,12 @@ int hisq_dslash_eo(hisq_gauge_t g, int out_parity, int prec, const void *in, voi
  * diag[i] = 4 m^2 + sigma_i and y = the even vectors that in = D_oe y was
  * formed from, this is (A + sigma_i) y_i.  For FP16S the epilogue output is
  * written as FP16S too.  The RHS tile and block shape come from the
- * autotuner's table (defaults if the shape was never tuned).
- * Errors: -1 bad arguments (nrhs < 1, y without diag), -4 precision not packed.
+ * autotuner's table (defaults if the shape was never tuned).  The stacks in
+ * and out (and y and out) must not overlap.  diag is copied to a buffer of
+ * the handle (grown, with a synchronisation, only for nrhs > 64); calls on
+ * different streams are ordered on the device around that buffer.
+ * Errors: -1 bad arguments (nrhs < 1, y without diag, overlapping stacks),
+ * -4 precision not packed.
  */
 int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in,
                           void *out, const double *diag, const void *y, void *stream);
@@ -317,7 +321,12 @@ int hisq_rational_remez(double power, double lmin, double lmax, int npole, doubl
 int hisq_spectral_bounds(hisq_gauge_t g, double mass, int iters, double *lmin, double *lmax, void *stream);
 
 /*
- * Gauge-covariant preconditioner network, z = N(r): a stack of linear layers
+ * Gauge-covariant preconditioner network, z = N(r) (not part of the paper's
+ * method: the learned preconditioner beside its CG family).  The layers are
+ * the linear parallel-transport layers of lattice gauge-equivariant networks
+ * (Favoni et al., Phys. Rev. Lett. 128 (2022) 032003), used as a
+ * preconditioner of the Dirac normal equations as by Lehner and Wettig
+ * (Phys. Rev. D 108 (2023) 034503): a stack of linear layers
  * psi'_a(x) = sum_b [ W0_ab psi_b(x) + sum_mu ( Wf_mu,ab U_mu(x) psi_b(x+mu)
  *                                            + Wb_mu,ab U_mu(x-mu)^+ psi_b(x-mu) ) ]
  * on the full lattice (the even input embedded with zeros on odd sites, the

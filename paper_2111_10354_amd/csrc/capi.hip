@@ -48,6 +48,12 @@ static int check_spinors(const void *a, const void *b, const void *c = nullptr) 
     return HISQ_OK;
 }
 
+// Two device buffers of na and nb bytes share memory (compared as addresses).
+static bool bytes_overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
 static int check_handle(hisq_gauge_t g) {
     if (!g) return fail(HISQ_ERR_INVALID, "gauge handle is NULL");
     return HISQ_OK;
@@ -72,6 +78,7 @@ hisq_gauge_s::~hisq_gauge_s() {
     cg_ws.clear();
     fcg_ws.reset();
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (diag_event) (void)hipEventDestroy(diag_event);
 }
 
 extern "C" {
@@ -174,6 +181,12 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
         }
     }
     e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->diag_event, hipEventDisableTiming);
+    // epilogue coefficients of up to 64 right-hand sides without a later allocation
+    if (e == hipSuccess && (rc = g->diag_buf.alloc(sizeof(double) * 64))) {
+        delete g;
+        return rc;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete g;
@@ -213,37 +226,59 @@ int hisq_dslash_eo(hisq_gauge_t g, int out_parity, int prec, const void *in, voi
     if (out_parity != 0 && out_parity != 1) return fail(HISQ_ERR_INVALID, "out_parity must be 0 or 1");
     if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
     if (!in || !out) return fail(HISQ_ERR_INVALID, "in and out are required");
-    if (in == out) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
     if ((rc = check_spinors(in, out))) return rc;
+    const size_t sb = spinor_bytes(prec, g->geom.vh);
+    if (bytes_overlap(in, sb, out, sb)) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
     return gauge_dslash(g, out_parity, prec, prec, prec, 1, in, out, nullptr, nullptr, nullptr, nullptr,
                         (hipStream_t)stream);
 }
 
-int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in, void *out,
-                          const double *diag, const void *y, void *stream) {
+}  // extern "C"
+
+// Argument checks of the multi-RHS entry points.
+int hisq::check_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in, void *out,
+                           const double *diag, const void *y) {
     int rc = check_handle(g);
     if (rc) return rc;
     if (out_parity != 0 && out_parity != 1) return fail(HISQ_ERR_INVALID, "out_parity must be 0 or 1");
     if (!valid_prec(prec)) return fail(HISQ_ERR_INVALID, "bad precision");
     if (nrhs < 1) return fail(HISQ_ERR_INVALID, "nrhs must be >= 1");
     if (!in || !out) return fail(HISQ_ERR_INVALID, "in and out are required");
-    if (in == out) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
     if ((diag == nullptr) != (y == nullptr)) return fail(HISQ_ERR_INVALID, "diag and y go together");
     if ((rc = check_spinors(in, out, y))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const double *ddev = nullptr;
-    double *part = nullptr;
-    if (diag) {
+    const size_t stack = spinor_bytes(prec, g->geom.vh) * (size_t)nrhs;
+    if (bytes_overlap(in, stack, out, stack)) return fail(HISQ_ERR_INVALID, "in and out must not overlap");
+    if (y && bytes_overlap(y, stack, out, stack)) return fail(HISQ_ERR_INVALID, "y and out must not overlap");
+    if (diag)
         for (int i = 0; i < nrhs; ++i)
             if (!std::isfinite(diag[i])) return fail(HISQ_ERR_INVALID, "diag must be finite");
-        std::lock_guard<std::mutex> lk(g->mu);
-        const size_t need = sizeof(double) * nrhs + sizeof(double) * (size_t)nrhs * ((g->geom.vh + 63) / 64);
+    return HISQ_OK;
+}
+
+extern "C" {
+
+int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in, void *out,
+                          const double *diag, const void *y, void *stream) {
+    int rc = check_multi_rhs(g, out_parity, prec, nrhs, in, out, diag, y);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!diag) return gauge_dslash(g, out_parity, prec, prec, prec, nrhs, in, out, nullptr, nullptr, nullptr, nullptr, s);
+    // The handle's coefficient buffer is reused by every epilogue call.  The
+    // lock covers copy and launch, and each call's copy waits (on the device)
+    // for the previous call's kernel, whatever stream either was issued on.
+    std::lock_guard<std::mutex> lk(g->mu);
+    const size_t need = sizeof(double) * nrhs;
+    if (g->diag_buf.bytes < need) {
+        HISQ_HIP_CHECK(hipEventSynchronize(g->diag_event));  // the old buffer may still be read
         if ((rc = g->diag_buf.alloc(need))) return rc;
-        HISQ_HIP_CHECK(hipMemcpyAsync(g->diag_buf.p, diag, sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-        ddev = (const double *)g->diag_buf.p;
-        part = (double *)g->diag_buf.p + nrhs;
     }
-    return gauge_dslash(g, out_parity, prec, prec, prec, nrhs, in, out, y, ddev, part, nullptr, s);
+    HISQ_HIP_CHECK(hipStreamWaitEvent(s, g->diag_event, 0));
+    HISQ_HIP_CHECK(hipMemcpyAsync(g->diag_buf.p, diag, need, hipMemcpyHostToDevice, s));
+    if ((rc = gauge_dslash(g, out_parity, prec, prec, prec, nrhs, in, out, y, (const double *)g->diag_buf.p,
+                           nullptr, nullptr, s)))
+        return rc;
+    HISQ_HIP_CHECK(hipEventRecord(g->diag_event, s));
+    return HISQ_OK;
 }
 
 int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double *x,
@@ -258,8 +293,9 @@ int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double
     if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
     if (nrhs < 1) return fail(HISQ_ERR_INVALID, "nrhs must be >= 1");
     if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
-    if (b == x) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
     if ((rc = check_spinors(b, x))) return rc;
+    const size_t stack = spinor_bytes(F64, g->geom.vh) * (size_t)nrhs;
+    if (bytes_overlap(b, stack, x, stack)) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
     std::lock_guard<std::mutex> lk(g->mu);
     if (prm.precond) {
         // flexible CG: one right-hand side after another
@@ -294,6 +330,8 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
             return fail(HISQ_ERR_INVALID, "every shift must be finite with sigma + 4 m^2 > 0");
     if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
     if ((rc = check_spinors(b, x))) return rc;
+    const size_t sb = spinor_bytes(F64, g->geom.vh);
+    if (bytes_overlap(b, sb, x, sb * (size_t)nshift)) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
     std::lock_guard<std::mutex> lk(g->mu);
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }
@@ -305,6 +343,22 @@ static bool ranges_overlap(const double *a, const double *b, int n) {
     return pa < pb + len && pb < pa + len;
 }
 
+// The coefficient outputs of the rational-approximation routines are written
+// one after another: none may share memory with another (alpha0 and delta are
+// single doubles, alpha and shift npole each).
+static int check_coefficient_outputs(int npole, const double *alpha0, const double *alpha, const double *shift,
+                                     const double *delta) {
+    if (ranges_overlap(alpha, shift, npole)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
+    for (const double *arr : {alpha, shift}) {
+        if (ranges_overlap(alpha0, arr, 1) || ranges_overlap(arr, alpha0, npole))
+            return fail(HISQ_ERR_INVALID, "alpha0 must not overlap alpha or shift");
+        if (delta && (ranges_overlap(delta, arr, 1) || ranges_overlap(arr, delta, npole)))
+            return fail(HISQ_ERR_INVALID, "delta must not overlap alpha or shift");
+    }
+    if (delta && ranges_overlap(delta, alpha0, 1)) return fail(HISQ_ERR_INVALID, "delta must not overlap alpha0");
+    return HISQ_OK;
+}
+
 int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0, double *alpha, double *shift,
                             double *delta) {
     if (!(lmin > 0.0) || !std::isfinite(lmin) || !std::isfinite(lmax) || !(lmax > lmin))
@@ -312,7 +366,8 @@ int hisq_zolotarev_inv_sqrt(double lmin, double lmax, int npole, double *alpha0,
     if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
-    if (ranges_overlap(alpha, shift, npole)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
+    int rc = check_coefficient_outputs(npole, alpha0, alpha, shift, delta);
+    if (rc) return rc;
     return zolotarev_inv_sqrt(lmin, lmax, npole, alpha0, alpha, shift, delta);
 }
 
@@ -325,7 +380,8 @@ int hisq_rational_remez(double power, double lmin, double lmax, int npole, doubl
     if (lmax / lmin > 1e14) return fail(HISQ_ERR_INVALID, "lmax / lmin must not exceed 1e14");
     if (npole < 1 || npole > 64) return fail(HISQ_ERR_INVALID, "1 <= npole <= 64");
     if (!alpha0 || !alpha || !shift) return fail(HISQ_ERR_INVALID, "alpha0, alpha and shift are required");
-    if (ranges_overlap(alpha, shift, npole)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
+    int rc = check_coefficient_outputs(npole, alpha0, alpha, shift, delta);
+    if (rc) return rc;
     // below ~1e-12 relative error the alternation drowns in rounding: the
     // x^(-1/2) optimum on the same interval measures how close that is
     {
@@ -360,8 +416,9 @@ int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, c
         if (!std::isfinite(alpha[k]) || !std::isfinite(shift[k]) || !(shift[k] + 4.0 * mass * mass > 0.0))
             return fail(HISQ_ERR_INVALID, "every alpha and shift must be finite with shift + 4 m^2 > 0");
     if (!b || !out) return fail(HISQ_ERR_INVALID, "b and out are required");
-    if (b == out) return fail(HISQ_ERR_INVALID, "b and out must not overlap");
     if ((rc = check_spinors(b, out))) return rc;
+    const size_t sb = spinor_bytes(F64, g->geom.vh);
+    if (bytes_overlap(b, sb, out, sb)) return fail(HISQ_ERR_INVALID, "b and out must not overlap");
     if (!g->links[F64][0].p) return fail(HISQ_ERR_UNSUPPORTED, "the handle lacks packed FP64 links");
     std::lock_guard<std::mutex> lk(g->mu);
     return rational_apply(g, mass, alpha0, nterm, alpha, shift, b, out, prm, st, (hipStream_t)stream);

@@ -9,8 +9,9 @@
 // load of a wavefront is one contiguous plane segment; the neighbour gathers
 // of a wavefront touch a contiguous run of sites shifted by the hop.
 //
-// Epilogue (optional): out_i = diag_i * y_i - (D in)_i and a per-block FP64
-// partial of Re <y_i, out_i>, which is what CG needs for <p, A p>.
+// Epilogue (optional): out_i = diag_i * y_i - (D in)_i and, if a partials
+// buffer is given, a per-block FP64 partial of Re <y_i, out_i>, which is what
+// CG needs for <p, A p>.
 //
 // The stencil is a 3x3 complex mat-vec per hop: 1146 flop per site against
 // 1200 bytes (FP32), far below the ridge point, so it is written for memory
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
     }
 
     if constexpr (EPI) {
+        if (!partials) return;  // uniform: the caller wants no <y, out>
         // deterministic block reduction: wave shuffles, then waves in order
         __shared__ double red[4][TILE];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

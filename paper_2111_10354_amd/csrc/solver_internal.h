@@ -122,6 +122,7 @@ struct hisq_gauge_s {
     hisq::DevBuf links[3][2];  // [format][output parity]
     bool compressed = false;   // FP32 / FP16 long links stored as two rows + determinant sign
     hisq::DevBuf diag_buf;     // epilogue coefficients for hisq_dslash_multi_rhs
+    hipEvent_t diag_event = nullptr;  // recorded after the last kernel that read diag_buf
     hisq::DevBuf thin;         // thin links (FP16) for the preconditioner network
     hipStream_t capture_stream = nullptr;
     std::mutex mu;
@@ -146,6 +147,11 @@ inline int sloppy_vec_fmt(int sloppy) { return sloppy == HISQ_PREC_FP16L ? F32 :
 inline bool links_compressed(const hisq_gauge_s *g, int fmt) { return g->compressed && fmt != F64; }
 
 DslashShape pick_shape(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi);
+
+// Argument checks shared by the multi-RHS Dslash entry points (HISQ_OK or an
+// error code with the message set).
+int check_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in, void *out,
+                    const double *diag, const void *y);
 
 // Dslash on the handle's packed links.
 int gauge_dslash(hisq_gauge_s *g, int out_parity, int fmt_links, int fmt_in, int fmt_out, int nrhs,

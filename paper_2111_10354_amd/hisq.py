@@ -135,6 +135,16 @@ def _ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _need(t, nbytes: int, what: str):
+    """Raise before any launch when a buffer is smaller than what the call
+    reads or writes (the C ABI sees only pointers)."""
+    if t is None:
+        return
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what}: {have} bytes, the call touches {nbytes}")
+
+
 def version() -> int:
     return LIB.hisq_version()
 
@@ -198,12 +208,20 @@ def gauge_create(dims, fat, lng, precs=("fp64", "fp32", "fp16s"), stream=None) -
 
 
 def dslash_eo(g: Gauge, out_parity: int, prec, inp: torch.Tensor, out: torch.Tensor, stream=None):
+    sb = spinor_bytes(prec, g.vh)
+    _need(inp, sb, "in")
+    _need(out, sb, "out")
     _check(LIB.hisq_dslash_eo(g.handle, int(out_parity), _prec(prec), _ptr(inp), _ptr(out), _stream(stream)))
 
 
 def dslash_multi_rhs(g: Gauge, out_parity: int, prec, nrhs: int, inp, out, diag=None, y=None, stream=None):
+    stack = spinor_bytes(prec, g.vh) * int(nrhs)
+    for t, what in ((inp, "in"), (out, "out"), (y, "y")):
+        _need(t, stack, what)
     dd = None
     if diag is not None:
+        if len(diag) < nrhs:
+            raise ValueError(f"diag: {len(diag)} values for {nrhs} right-hand sides")
         dd = (C.c_double * nrhs)(*[float(v) for v in diag])
     _check(LIB.hisq_dslash_multi_rhs(g.handle, int(out_parity), _prec(prec), int(nrhs), _ptr(inp), _ptr(out),
                                      dd, _ptr(y), _stream(stream)))
@@ -225,6 +243,9 @@ def solver_params(**kw) -> SolverParams:
 
 def cg_solve(g: Gauge, mass: float, nrhs: int, b, x, params: SolverParams | None = None, stream=None):
     """Returns (status, [stats dict per RHS])."""
+    stack = spinor_bytes("fp64", g.vh) * int(nrhs)
+    _need(b, stack, "b")
+    _need(x, stack, "x")
     st = (SolverStats * nrhs)()
     rc = LIB.hisq_cg_solve(g.handle, float(mass), int(nrhs), _ptr(b), _ptr(x),
                            C.byref(params) if params is not None else None, st, _stream(stream))
@@ -234,6 +255,9 @@ def cg_solve(g: Gauge, mass: float, nrhs: int, b, x, params: SolverParams | None
 
 def multishift_cg(g: Gauge, mass: float, shifts, b, x, params: SolverParams | None = None, stream=None):
     n = len(shifts)
+    sb = spinor_bytes("fp64", g.vh)
+    _need(b, sb, "b")
+    _need(x, sb * n, "x")
     sh = (C.c_double * n)(*[float(v) for v in shifts])
     st = (SolverStats * n)()
     rc = LIB.hisq_multishift_cg(g.handle, float(mass), n, sh, _ptr(b), _ptr(x),
@@ -248,6 +272,9 @@ def rational_apply(g: Gauge, mass: float, alpha0: float, alphas, shifts, b, out,
     n = len(shifts)
     if len(alphas) != n:
         raise ValueError("alphas and shifts differ in length")
+    sb = spinor_bytes("fp64", g.vh)
+    _need(b, sb, "b")
+    _need(out, sb, "out")
     al = (C.c_double * max(n, 1))(*[float(v) for v in alphas])
     sh = (C.c_double * max(n, 1))(*[float(v) for v in shifts])
     st = (SolverStats * max(n, 1))()
@@ -299,6 +326,7 @@ def dslash_shape(g: Gauge, prec, nrhs: int, epilogue: int = 0):
 
 def gauge_set_thin(g: Gauge, thin: torch.Tensor, stream=None):
     """Thin links (complex128 [V,4,3,3] device tensor, phases folded) for the network."""
+    _need(thin, 2 * g.vh * 4 * 9 * 16, "thin")
     _check(LIB.hisq_gauge_set_thin(g.handle, _ptr(thin), _stream(stream)))
 
 
@@ -308,6 +336,7 @@ class Net:
     def __init__(self, g: Gauge, channels, weights=None, stream=None):
         import numpy as np
         self.channels = tuple(int(c) for c in channels)
+        self.vh = g.vh
         nl = len(self.channels) - 1
         ch = (C.c_int * (nl + 1))(*self.channels)
         w = None
@@ -335,8 +364,14 @@ class Net:
         _check(LIB.hisq_nn_set_weights(self.handle, wa.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
                                        _stream(stream)))
 
+    def _pairs(self, batch, av, v):
+        stack = spinor_bytes("fp32", self.vh) * int(batch)
+        _need(av, stack, "av")
+        _need(v, stack, "v")
+
     def loss_grad(self, batch, av, v, want_grad=True, stream=None):
         import numpy as np
+        self._pairs(batch, av, v)
         loss = C.c_double()
         grad = np.zeros(self.n, np.complex128) if want_grad else None
         gp = grad.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)) if want_grad else None
@@ -344,6 +379,7 @@ class Net:
         return loss.value, grad
 
     def train_step(self, batch, av, v, lr, stream=None):
+        self._pairs(batch, av, v)
         loss = C.c_double()
         _check(LIB.hisq_nn_train_step(self.handle, int(batch), _ptr(av), _ptr(v), float(lr), C.byref(loss),
                                       _stream(stream)))
@@ -362,4 +398,7 @@ class Net:
 
 
 def precond_apply(g: Gauge, net: Net, inp, out, stream=None):
+    sb = spinor_bytes("fp32", g.vh)
+    _need(inp, sb, "in")
+    _need(out, sb, "out")
     _check(LIB.hisq_precond_apply(g.handle, net.handle, _ptr(inp), _ptr(out), _stream(stream)))

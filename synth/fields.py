@@ -193,8 +193,75 @@ def _run(fn, items, workers):
             fn(i)
         return
     ctx = mp.get_context("fork")
-    with ctx.Pool(min(workers, len(items))) as pool:
+    pool = ctx.Pool(min(workers, len(items)))
+    try:
         pool.map(fn, items, chunksize=1)
+    except BaseException:
+        pool.terminate()
+        pool.join()
+        raise
+    # let the workers finish and exit by themselves: terminate() would end them
+    # with SIGTERM, which a profiler's signal handler in the process reports as
+    # an abort
+    pool.close()
+    pool.join()
+
+
+def _gpu_initialised() -> bool:
+    """True if this process has already set up the GPU through torch (forking
+    worker processes from it is then avoided)."""
+    import sys
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:
+        return False
+
+
+def _memfd_array(shape, dtype=np.complex128):
+    """(array, fd): an array in anonymous shared memory that a child process
+    can map through the inherited file descriptor."""
+    nbytes = max(int(np.prod(shape)) * np.dtype(dtype).itemsize, 1)
+    fd = os.memfd_create("hisq_synth_links")
+    os.ftruncate(fd, nbytes)
+    buf = mmap.mmap(fd, nbytes)
+    return np.frombuffer(buf, dtype=dtype, count=int(np.prod(shape))).reshape(shape), fd
+
+
+def _in_child(kind, nout, V, **kw):
+    """Run the generator `kind` ("thin" or "hisq") in a fresh Python interpreter
+    (its own fork pool, no GPU state) that writes `nout` link fields into shared
+    memory kept by this process.  Used once this process has initialised the
+    GPU, where forking workers is avoided."""
+    import json
+    import subprocess
+    import sys
+    outs = [_memfd_array((V, 4, 3, 3)) for _ in range(nout)]
+    fds = [fd for _, fd in outs]
+    spec = json.dumps(dict(kind=kind, fds=fds, **kw))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, sys.argv[1]); "
+            "from synth import fields; fields._child_main(sys.argv[2])")
+    try:
+        subprocess.run([sys.executable, "-c", code, root, spec], pass_fds=fds, check=True)
+    finally:
+        for fd in fds:
+            os.close(fd)  # the mappings stay valid
+    return tuple(a for a, _ in outs)
+
+
+def _child_main(spec: str):
+    import json
+    d = json.loads(spec)
+    dims = tuple(d["dims"])
+    V = volume(dims)
+    arrs = [np.frombuffer(mmap.mmap(fd, V * 4 * 9 * 16), dtype=np.complex128).reshape(V, 4, 3, 3)
+            for fd in d["fds"]]
+    if d["kind"] == "thin":
+        thin_links(dims, d["cfg_id"], d["eps"], out=arrs[0])
+    else:
+        hisq_links(dims, d["cfg_id"], d["eps"], antiperiodic_t=d["apbc"], want_thin=len(arrs) == 3,
+                   fold=d["fold"], out=arrs)
 
 
 def _default_workers(V: int) -> int:
@@ -203,12 +270,17 @@ def _default_workers(V: int) -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def thin_links(dims, cfg_id: int, eps: float, workers: int | None = None) -> np.ndarray:
-    """Unfolded thin links U = exp(i eps H), shape (V, 4, 3, 3)."""
+def thin_links(dims, cfg_id: int, eps: float, workers: int | None = None, out=None) -> np.ndarray:
+    """Unfolded thin links U = exp(i eps H), shape (V, 4, 3, 3) (into `out` if given)."""
     _check_dims(dims)
     V = volume(dims)
     workers = _default_workers(V) if workers is None else workers
-    U = _shared_array((V, 4, 3, 3)) if workers > 1 else np.empty((V, 4, 3, 3), np.complex128)
+    if out is None and workers > 1 and _gpu_initialised():
+        return _in_child("thin", 1, V, dims=list(dims), cfg_id=cfg_id, eps=eps)[0]
+    if out is not None:
+        U = out
+    else:
+        U = _shared_array((V, 4, 3, 3)) if workers > 1 else np.empty((V, 4, 3, 3), np.complex128)
     _SHARED.clear()
     _SHARED.update(dims=tuple(dims), cfg_id=cfg_id, eps=eps, U=U)
     try:
@@ -219,22 +291,34 @@ def thin_links(dims, cfg_id: int, eps: float, workers: int | None = None) -> np.
 
 
 def hisq_links(dims, cfg_id: int, eps: float, antiperiodic_t: bool = False,
-               want_thin: bool = False, workers: int | None = None, fold: bool = True):
+               want_thin: bool = False, workers: int | None = None, fold: bool = True, out=None):
     """Folded fat and Naik links of the benchmark recipe.
 
     Returns ``(fat, long)`` or ``(fat, long, thin)`` where ``thin`` is the thin
     field with the same phases and one-hop boundary signs folded in.  With
     ``fold=False`` no phase or boundary sign is applied (used to check the
-    folding against an operator that applies them itself).
+    folding against an operator that applies them itself).  ``out``: arrays
+    (shared with forked workers) to write the result into.
+
+    Large lattices are built by a pool of forked worker processes.  Once this
+    process has initialised the GPU, the pool runs in a fresh child interpreter
+    instead, which writes into shared memory kept by this process.
     """
     _check_dims(dims)
     V = volume(dims)
     workers = _default_workers(V) if workers is None else workers
+    if out is None and workers > 1 and _gpu_initialised():
+        return _in_child("hisq", 3 if want_thin else 2, V, dims=list(dims), cfg_id=cfg_id, eps=eps,
+                         apbc=bool(antiperiodic_t), fold=bool(fold))
     U = thin_links(dims, cfg_id, eps, workers)
     alloc = (lambda: _shared_array((V, 4, 3, 3))) if workers > 1 else \
         (lambda: np.empty((V, 4, 3, 3), np.complex128))
-    F, L = alloc(), alloc()
-    T = alloc() if want_thin else None
+    if out is not None:
+        F, L = out[0], out[1]
+        T = out[2] if want_thin else None
+    else:
+        F, L = alloc(), alloc()
+        T = alloc() if want_thin else None
     _SHARED.clear()
     _SHARED.update(dims=tuple(dims), cfg_id=cfg_id, apbc=bool(antiperiodic_t), U=U, F=F, L=L, T=T,
                    fold=bool(fold))

@@ -158,3 +158,52 @@ def test_bench_traffic_is_keyed_on_sources_layout_and_shape():
     assert bench.counter_traffic(dims, rec["long_links_compressed"], (shape[0], shape[1], shape[2] + 1)) is None
     assert bench.counter_traffic(dims, not rec["long_links_compressed"], shape) is None
     assert bench.counter_traffic((48, 48, 48, 12), False, shape) is None
+
+
+def test_coefficient_scalar_outputs_must_not_alias_the_arrays():
+    """alpha0 and delta are written before (and read back after) the arrays:
+    any of them inside alpha or shift, or delta on alpha0, is refused."""
+    from paper_2111_10354_amd import hisq
+    L = hisq.LIB
+    n = 4
+    for fn, args in ((L.hisq_zolotarev_inv_sqrt, (1e-3, 1.0)), (L.hisq_rational_remez, (0.25, 1e-3, 1.0))):
+        al, sh = (C.c_double * n)(), (C.c_double * n)()
+        a0, dl = C.c_double(), C.c_double()
+        elem = lambda arr, i: C.cast(C.byref(arr, 8 * i), C.POINTER(C.c_double))  # noqa: E731
+        for bad in ((elem(al, 2), al, sh, C.byref(dl)),      # alpha0 inside alpha
+                    (elem(sh, 0), al, sh, C.byref(dl)),      # alpha0 inside shift
+                    (C.byref(a0), al, sh, elem(al, 3)),      # delta inside alpha
+                    (C.byref(a0), al, sh, elem(sh, 1)),      # delta inside shift
+                    (C.byref(a0), al, sh, C.byref(a0))):     # delta on alpha0
+            assert fn(*args, n, *bad) == hisq.ERR_INVALID
+            assert "overlap" in hisq.last_error()
+        assert fn(*args, n, C.byref(a0), al, sh, C.byref(dl)) == hisq.OK
+        assert dl.value > 0 and all(v > 0 for v in sh)
+
+
+def test_binding_rejects_undersized_buffers_before_any_call():
+    """The C ABI sees only pointers: the binding compares every buffer with the
+    bytes the call touches and raises before anything reaches the library (the
+    handle here is a stand-in that the library never sees)."""
+    import torch
+    from paper_2111_10354_amd import hisq
+    g = hisq.Gauge.__new__(hisq.Gauge)
+    g.dims, g.vh, g.handle = (8, 8, 8, 8), 2048, None
+    one32 = torch.empty(hisq.spinor_bytes("fp32", g.vh), dtype=torch.uint8)
+    one64 = torch.empty(hisq.spinor_bytes("fp64", g.vh), dtype=torch.uint8)
+    short = one32[:-16]
+    calls = [
+        lambda: hisq.dslash_eo(g, 0, "fp32", short, one32),
+        lambda: hisq.dslash_eo(g, 0, "fp32", one32, short),
+        lambda: hisq.dslash_eo(g, 0, "fp64", one32, one64),           # fp32-sized input for fp64
+        lambda: hisq.dslash_multi_rhs(g, 0, "fp32", 4, one32, one32),  # a 1-RHS buffer with nrhs = 4
+        lambda: hisq.dslash_multi_rhs(g, 0, "fp32", 1, one32, one32, diag=[1.0], y=short),
+        lambda: hisq.cg_solve(g, 0.1, 2, one64, one64),
+        lambda: hisq.multishift_cg(g, 0.1, [0.0, 0.1], one64, one64),  # x holds one of two shifts
+        lambda: hisq.rational_apply(g, 0.1, 1.0, [1.0], [0.1], one32, one64),
+        lambda: hisq.precond_apply(g, None, one32[:-8], one32),
+        lambda: hisq.gauge_set_thin(g, one64),
+    ]
+    for i, call in enumerate(calls):
+        with pytest.raises(ValueError):
+            call()

@@ -268,3 +268,63 @@ def test_rejects_unpacked_precision():
         hisq().dslash_eo(g, 0, "fp64", buf, out)
     assert e.value.code == hisq().ERR_UNSUPPORTED
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_epilogue_calls_on_two_streams(gauges, prec):
+    """Two epilogue calls with different coefficients, issued back to back on two
+    streams with no host synchronisation between them: the first call's kernel is
+    held back behind a spin on its stream, so without device-side ordering the
+    second call's coefficients would reach the first call's kernel.  Both outputs
+    must be their own (A + sigma) y against the oracle."""
+    import torch
+    dims = (8, 8, 8, 8)
+    g, F, L = gauges(dims)
+    vh = synth.volume(dims) // 2
+    mass = 0.1
+    nb = spinor_nbytes(prec, vh)
+    ys = synth.gaussian_source(dims, 99, 2, parity=0, index0=60)
+    raw = np.concatenate([encode(to_cb(dims, y, 0), prec) for y in ys])
+    y = to_device(raw)
+    t = torch.empty(2 * nb, dtype=torch.uint8, device="cuda")
+    hisq().dslash_multi_rhs(g, 1, prec, 2, y, t)
+    torch.cuda.synchronize()
+    sig = [(0.0, 0.25), (3.0, 0.5)]
+    outs = [torch.empty(2 * nb, dtype=torch.uint8, device="cuda") for _ in sig]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        torch.cuda._sleep(50_000_000)   # a bounded spin: the first kernel starts late
+        hisq().dslash_multi_rhs(g, 0, prec, 2, t, outs[0], diag=[4 * mass * mass + v for v in sig[0]], y=y,
+                                stream=s1)
+    with torch.cuda.stream(s2):
+        hisq().dslash_multi_rhs(g, 0, prec, 2, t, outs[1], diag=[4 * mass * mass + v for v in sig[1]], y=y,
+                                stream=s2)
+    torch.cuda.synchronize()
+    tol = {"fp64": 1e-13, "fp32": 2e-6}[prec]
+    for k, o in enumerate(outs):
+        got = to_host(o).reshape(2, -1)
+        for i in range(2):
+            yq = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 0)
+            want = to_cb(dims, oracle.normal_op(dims, F, L, mass, yq, sigma=sig[k][i]), 0)
+            assert rel_l2(decode(got[i], vh, prec), want) <= tol, (k, i)
+
+
+def test_overlapping_stacks_rejected(gauges):
+    """A partial overlap of two stacks (out one RHS past in, x overlapping b's
+    stack) is refused before any launch, like an exact alias."""
+    import torch
+    dims = (8, 8, 8, 8)
+    g, F, L = gauges(dims)
+    vh = synth.volume(dims) // 2
+    nb = spinor_nbytes("fp64", vh)
+    buf = torch.zeros(3 * nb, dtype=torch.uint8, device="cuda")
+    H = hisq()
+    cases = [lambda: H.dslash_multi_rhs(g, 0, "fp64", 2, buf[:2 * nb], buf[nb:]),
+             lambda: H.dslash_multi_rhs(g, 0, "fp64", 2, buf[nb:], buf[:2 * nb]),
+             lambda: H.dslash_multi_rhs(g, 0, "fp64", 1, buf[:nb], buf[2 * nb:], diag=[1.0], y=buf[2 * nb:]),
+             lambda: H.dslash_eo(g, 0, "fp64", buf[:nb], buf[nb - 16:2 * nb - 16]),
+             lambda: H.cg_solve(g, 0.1, 2, buf[:2 * nb], buf[nb:])]
+    for i, call in enumerate(cases):
+        with pytest.raises(H.HisqError) as e:
+            call()
+        assert e.value.code == H.ERR_INVALID and "overlap" in H.last_error(), i
