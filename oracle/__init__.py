@@ -17,7 +17,9 @@ Parts:
 * ``nn``: the gauge-covariant preconditioner network and its gradient;
 * ``rational``: rational functions of the normal operator (partial-fraction
   sums by independent CGs, exact dense powers, Zolotarev's approximation of
-  x^(-1/2)).
+  x^(-1/2));
+* ``smear``: HISQ link smearing (fat7, U(3) projection, fat7 with Lepage term,
+  Naik links) in FP64 numpy.
 """
 
 from .core import (  # noqa: F401
