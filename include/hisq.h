@@ -159,6 +159,24 @@ int hisq_dslash_multi_rhs(hisq_gauge_t g, int out_parity, int prec, int nrhs, co
                           void *out, const double *diag, const void *y, void *stream);
 
 /*
+ * hisq_dslash_multi_rhs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, semantics and output.  The per-RHS epilogue
+ * coefficients are staged in a fixed device array of HISQ_NOALLOC_MAX_RHS
+ * doubles per GPU, set up by hisq_gauge_create and kept until the process
+ * ends, so the call allocates nothing.  Every call on one GPU shares that
+ * array: calls with diag that overlap in time on one GPU (different streams
+ * or threads without ordering) race on it; calls ordered on one stream do
+ * not.  diag is read during the call (host), y/in/out as for
+ * hisq_dslash_multi_rhs.
+ * Errors: those of hisq_dslash_multi_rhs, and -1 if diag is given with nrhs >
+ * HISQ_NOALLOC_MAX_RHS.
+ */
+#define HISQ_NOALLOC_MAX_RHS 4096
+int hisq_dslash_multi_rhs_noalloc(hisq_gauge_t g, int out_parity, int prec, int nrhs, const void *in,
+                                  void *out, const double *diag, const void *y, void *stream);
+
+/*
  * Autotune the Dslash launch shape (RHS tile per thread: 1, 2, 4, 8 or 16, at
  * most 4 with FP64 links; block size 64, 128 or 256; order in which the
  * 64-site tiles are processed: memory order, t-fastest planes, or XCD bricks

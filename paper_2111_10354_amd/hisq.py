@@ -61,6 +61,7 @@ def _load():
         "hisq_gauge_device_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
         "hisq_dslash_eo": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp]),
         "hisq_dslash_multi_rhs": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, dp, vp, vp]),
+        "hisq_dslash_multi_rhs_noalloc": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, dp, vp, vp]),
         "hisq_solver_params_default": (None, [C.POINTER(SolverParams)]),
         "hisq_cg_solve": (C.c_int, [vp, C.c_double, C.c_int, vp, vp, C.POINTER(SolverParams),
                                     C.POINTER(SolverStats), vp]),
@@ -100,7 +101,8 @@ EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_c
            "hisq_autotune", "hisq_dslash_shape", "hisq_gauge_set_thin", "hisq_nn_create", "hisq_nn_destroy",
            "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
            "hisq_nn_train_step", "hisq_gauge_links_compressed", "hisq_rational_apply",
-           "hisq_zolotarev_inv_sqrt", "hisq_rational_remez", "hisq_spectral_bounds")
+           "hisq_zolotarev_inv_sqrt", "hisq_rational_remez", "hisq_spectral_bounds",
+           "hisq_dslash_multi_rhs_noalloc")
 
 LINKS_FULL = 1 << 8  # hisq_gauge_create: store every link whole
 
@@ -225,6 +227,21 @@ def dslash_multi_rhs(g: Gauge, out_parity: int, prec, nrhs: int, inp, out, diag=
         dd = (C.c_double * nrhs)(*[float(v) for v in diag])
     _check(LIB.hisq_dslash_multi_rhs(g.handle, int(out_parity), _prec(prec), int(nrhs), _ptr(inp), _ptr(out),
                                      dd, _ptr(y), _stream(stream)))
+
+
+def dslash_multi_rhs_noalloc(g: Gauge, out_parity: int, prec, nrhs: int, inp, out, diag=None, y=None,
+                             stream=None):
+    """dslash_multi_rhs through the entry point that allocates no device memory."""
+    stack = spinor_bytes(prec, g.vh) * int(nrhs)
+    for t, what in ((inp, "in"), (out, "out"), (y, "y")):
+        _need(t, stack, what)
+    dd = None
+    if diag is not None:
+        if len(diag) < nrhs:
+            raise ValueError(f"diag: {len(diag)} values for {nrhs} right-hand sides")
+        dd = (C.c_double * nrhs)(*[float(v) for v in diag])
+    _check(LIB.hisq_dslash_multi_rhs_noalloc(g.handle, int(out_parity), _prec(prec), int(nrhs), _ptr(inp),
+                                             _ptr(out), dd, _ptr(y), _stream(stream)))
 
 
 def solver_params(**kw) -> SolverParams:
