@@ -36,6 +36,11 @@
 
 typedef double _Complex cplx;
 
+/* Site loops run on several threads only on lattices large enough to pay for
+ * them (on the tiny test lattices the thread start-up costs more than the
+ * work, and a busy host makes it far worse). */
+#define OMP_MIN_SITES 32768
+
 static long site_volume(const int L[4]) { return (long)L[0] * L[1] * L[2] * L[3]; }
 
 static void lex_to_coords(const int L[4], long s, int c[4]) {
@@ -89,7 +94,7 @@ void oracle_dslash(const int L[4], const double *fat_, const double *lng_,
     const cplx *F = (const cplx *)fat_, *N = (const cplx *)lng_, *in = (const cplx *)in_;
     cplx *out = (cplx *)out_;
     const long V = site_volume(L);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (V >= OMP_MIN_SITES)
     for (long s = 0; s < V; ++s) {
         cplx acc[3] = {0, 0, 0};
         if (parity_of(L, s) == out_parity) {
@@ -112,7 +117,7 @@ void oracle_dslash_sites(const int L[4], const double *fat_, const double *lng_,
                          const int64_t *sites, long nsites, double *out_) {
     const cplx *F = (const cplx *)fat_, *N = (const cplx *)lng_, *in = (const cplx *)in_;
     cplx *out = (cplx *)out_;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nsites >= 256)
     for (long i = 0; i < nsites; ++i) {
         const long s = (long)sites[i];
         cplx acc[3] = {0, 0, 0};
@@ -146,7 +151,7 @@ void oracle_dslash_phased(const int L[4], const double *fat_, const double *lng_
     const cplx *F = (const cplx *)fat_, *N = (const cplx *)lng_, *in = (const cplx *)in_;
     cplx *out = (cplx *)out_;
     const long V = site_volume(L);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (V >= OMP_MIN_SITES)
     for (long s = 0; s < V; ++s) {
         cplx acc[3] = {0, 0, 0};
         int c[4];
@@ -181,7 +186,7 @@ void oracle_normal_op(const int L[4], const double *fat, const double *lng, doub
     oracle_dslash(L, fat, lng, in_, tmp, 1);
     oracle_dslash(L, fat, lng, tmp, out_, 0);
     const double diag = 4.0 * mass * mass + sigma;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (V >= OMP_MIN_SITES)
     for (long s = 0; s < V; ++s) {
         if (parity_of(L, s) != 0) continue;
         for (int a = 0; a < 3; ++a) out[s * 3 + a] = diag * in[s * 3 + a] - out[s * 3 + a];
@@ -191,7 +196,7 @@ void oracle_normal_op(const int L[4], const double *fat, const double *lng, doub
 /* <u, v> = sum conj(u) v over all components (odd sites are zero). */
 static cplx vdot(long n, const cplx *u, const cplx *v) {
     double re = 0, im = 0;
-#pragma omp parallel for reduction(+ : re, im) schedule(static)
+#pragma omp parallel for reduction(+ : re, im) schedule(static) if (n >= 3 * OMP_MIN_SITES)
     for (long i = 0; i < n; ++i) {
         cplx t = conj(u[i]) * v[i];
         re += creal(t);

@@ -113,6 +113,41 @@ def fold(dims, X, L, antiperiodic_t=False):
     return X * sx[:, :, None, None], L * sl[:, :, None, None]
 
 
+PATCH_RADIUS = 5
+
+
+def hisq_smear_at(dims, U, site, antiperiodic_t=False):
+    """(fat, long) [4,3,3] at one lexicographic site, phases folded, from the
+    patch of thin links within PATCH_RADIUS steps of it in every direction.
+
+    The fat link at x depends on W within two steps (the Lepage paths) and one
+    step ahead along its own direction, and each W on U within one step (plus
+    one ahead); the Naik link on W at x, x + mu, x + 2mu.  No path from x leaves
+    the patch, so smearing the patch as a periodic lattice of extent 11 gives
+    the full lattice's values at its centre (for any lattice extents)."""
+    R = PATCH_RADIUS
+    P = 2 * R + 1
+    Lx, Ly, Lz, Lt = dims
+    c0 = np.array([site % Lx, (site // Lx) % Ly, (site // (Lx * Ly)) % Lz, site // (Lx * Ly * Lz)])
+    d = np.arange(-R, R + 1)
+    t, z, y, x = np.meshgrid((c0[3] + d) % Lt, (c0[2] + d) % Lz, (c0[1] + d) % Ly, (c0[0] + d) % Lx,
+                             indexing="ij")
+    lex = (x + Lx * (y + Ly * (z + Lz * t))).ravel()
+    pd = (P, P, P, P)
+    Up = U[lex]
+    W = u3_project(fat7(pd, Up, Up, **LEVEL1))
+    X = fat7(pd, W, W, **LEVEL2)
+    L = naik(pd, W)
+    centre = R + P * (R + P * (R + P * R))
+    # phases and boundary signs of the site's global coordinates
+    eta = np.array([1.0, (-1.0) ** c0[0], (-1.0) ** (c0[0] + c0[1]), (-1.0) ** (c0[0] + c0[1] + c0[2])])
+    sx, sl = eta.copy(), eta.copy()
+    if antiperiodic_t:
+        sx[3] *= -1.0 if c0[3] + 1 >= Lt else 1.0
+        sl[3] *= -1.0 if c0[3] + 3 >= Lt else 1.0
+    return X[centre] * sx[:, None, None], L[centre] * sl[:, None, None]
+
+
 def hisq_smear(dims, U, antiperiodic_t=False, want_levels=False):
     """(fat, long) HISQ links from thin links U [V,4,3,3], phases folded; with
     want_levels also the level-1 V and the projected W (unfolded)."""

@@ -151,3 +151,14 @@ def test_gauge_covariance_of_every_level(apbc):
     assert np.abs(W.conj().swapaxes(-1, -2) @ W - np.eye(3)).max() < 1e-13
     LL = L.conj().swapaxes(-1, -2) @ L
     assert np.abs(LL - np.eye(3) / 24 ** 2).max() < 1e-15
+
+
+@pytest.mark.parametrize("dims,apbc", [((4, 4, 4, 6), False), ((6, 4, 8, 4), True)])
+def test_patch_smearing_equals_whole_lattice(dims, apbc):
+    """The single-site evaluation (patch of radius 5, used to check large
+    lattices at sampled sites) gives the whole-lattice result at every site."""
+    U = synth.thin_links(dims, 98, 0.7)
+    F, L = smear.hisq_smear(dims, U, antiperiodic_t=apbc)
+    for site in np.random.default_rng(0).choice(synth.volume(dims), 4, replace=False):
+        f, l = smear.hisq_smear_at(dims, U, int(site), antiperiodic_t=apbc)
+        assert np.abs(f - F[site]).max() < 1e-13 and np.abs(l - L[site]).max() < 1e-13
