@@ -106,19 +106,53 @@ size_t hisq_spinor_bytes(int prec, int64_t vh);
  *            optionally HISQ_LINKS_FULL.  FP16 links need every entry below
  *            2^14 in magnitude.
  * Gauge-field compression (the paper's D-slash, Sec. 3: store part of each
- * link, recompute the rest from its unitarity): unless HISQ_LINKS_FULL is
- * set, when every long link is unitary with determinant +1 or -1 (deviation
- * at most 1e-12 in FP64) the FP32 and FP16 copies store only its first two
- * rows and the kernels rebuild the third as det * conj(row0 x row1).  The fat
- * links, and every link of the FP64 copy (which carries the true residual),
- * stay whole.  hisq_gauge_links_compressed() reports the choice.
+ * link, recompute the rest from its SU(3) or U(3) structure): unless
+ * HISQ_LINKS_FULL is set, the FP32 and FP16 copies store only the first two
+ * rows of each long link and the kernels rebuild the third as
+ * kappa * conj(row0 x row1), which holds for any multiple M = s U of a
+ * unitary U with kappa = det(M) / s^4.  When every long link is unitary with
+ * determinant +1 or -1 (deviation at most 1e-12 in FP64: SU(3) products with
+ * the signs folded in) kappa is a sign bit per link (mode 1); otherwise, when
+ * every long link is a positive multiple of a unitary matrix (relative
+ * deviation at most 1e-12: the U(3)-projected HISQ Naik links), kappa is
+ * stored as a complex number per link (mode 2).  The fat links, and every
+ * link of the FP64 copy (which carries the true residual), stay whole.
+ * hisq_gauge_links_compressed() reports the choice.
  * On success *out receives the handle.  Errors: -1 bad dims / null pointers /
  * empty mask, -3 out of memory, -2 HIP failure.
  */
 int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
                       unsigned prec_mask, void *stream);
 
-/* 1 if the handle's FP32 / FP16 long links are compressed, 0 if whole, -1 for NULL. */
+/*
+ * HISQ link smearing: the fat and Naik links of the HISQ action (Follana et
+ * al., Phys. Rev. D 75 (2007) 054502; the action of the paper's HotQCD
+ * ensembles, Sec. 1) from the thin gauge links, in FP64:
+ *   V = fat7[U]      one-link 1/8, 3-staple 1/16, 5-staple 1/64, 7-staple
+ *                    1/384 (every ordering of the transverse directions)
+ *   W = V (V^+ V)^(-1/2)                           (projection onto U(3))
+ *   X = fat7[W] with one-link 1 and the Lepage (two-step staple) term -1/8
+ *   L_mu(x) = -1/24 W_mu(x) W_mu(x+mu) W_mu(x+2mu)
+ * with the staggered phases and boundary signs folded in, so fat = X and
+ * lng = L go straight to hisq_gauge_create.  Unit links give 9/8 and -1/24.
+ * The Naik links are multiples of U(3) matrices: hisq_gauge_create stores
+ * them compressed (two rows and a complex factor, see there).
+ *   dims      host int[4], as for hisq_gauge_create
+ *   thin      device, complex double [V][4][3][3] gauge links without phases
+ *             (periodic gauge field), canonical layout; only read
+ *   fat, lng  device outputs in the same layout; none of the three may overlap
+ *   flags     HISQ_SMEAR_ANTIPERIODIC_T: fold the antiperiodic time boundary
+ *             sign (-1 on t links with t + 1 >= Lt, Naik links t + 3 >= Lt)
+ * Allocates a workspace of 6 link fields of one direction (864 V bytes) for
+ * the call.  Synchronous.  Errors: -1 bad dims, pointers, flags or overlap,
+ * -3 out of memory, -2 HIP failure.
+ */
+#define HISQ_SMEAR_ANTIPERIODIC_T 1u
+int hisq_smear_links(const int dims[4], const double *thin, double *fat, double *lng, unsigned flags,
+                     void *stream);
+
+/* Compression of the handle's FP32 / FP16 long links: 0 whole, 1 two rows and
+ * a determinant sign bit, 2 two rows and a complex factor; -1 for NULL. */
 int hisq_gauge_links_compressed(hisq_gauge_t g);
 
 /* Release the handle and everything it owns (NULL is accepted). */
@@ -216,6 +250,10 @@ typedef struct {
     int fallback;      /* nonzero: after a breakdown or stagnation of a mixed or
                           preconditioned solve, finish with plain FP64 CG (1) */
     hisq_nn_t precond; /* NULL, or a network: flexible CG with z = N(r) (NULL) */
+    double ru_delta;   /* mixed precision: a reliable update also when the iterated
+                          residual norm has fallen by this factor since the last
+                          one, in [0, 1); 0 = by ru_period and convergence only
+                          (0.1) */
 } hisq_solver_params;
 
 /* Per right-hand side (or per shift) solver report. */

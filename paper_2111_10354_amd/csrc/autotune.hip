@@ -1,8 +1,9 @@
 // Autotuner for the Dslash launch shape.
 //
 // For one (link precision, input/output formats, number of RHS, epilogue) it
-// times every candidate (RHS tile per thread, block size, tile processing
-// order) on the handle's own links with HIP events, after checking that the
+// times every candidate (RHS tile per thread, number of waves a site's RHS
+// tiles are split over, block size, tile processing order) on the handle's
+// own links with HIP events, after checking that the
 // candidate writes exactly the bytes the default shape writes (every shape
 // performs the same per-site arithmetic in the same order).  The fastest shape
 // is installed in the handle and, if a cache file is given, appended to it as
@@ -69,7 +70,7 @@ static std::string arch_name(int dev) {
 static std::string tune_key(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi) {
     std::ostringstream k;
     k << arch_name(g->device) << "|" << fl << fi << fo << "|" << g->dims[0] << "x" << g->dims[1] << "x" << g->dims[2]
-      << "x" << g->dims[3] << "|n" << nrhs << "|e" << (int)epi << (links_compressed(g, fl) ? "|c" : "");
+      << "x" << g->dims[3] << "|n" << nrhs << "|e" << (int)epi << (links_compressed(g, fl) == COMP_SIGN ? "|c" : links_compressed(g, fl) == COMP_KAPPA ? "|u" : "");
     return k.str();
 }
 
@@ -130,10 +131,17 @@ static std::vector<int> brick_orders(const Geom &G, int fi, int tile) {
     return o;
 }
 
+// RHS split of a shape (bits 24-25 of its order: waves sharing a site's links)
+static int shape_rsplit(const DslashShape &s) { return 1 << ((s.order >> 24) & 3); }
+
 static bool valid_shape(const Geom &geom, int fl, int nrhs, const DslashShape &s) {
     if (s.tile < 1 || s.tile > 16 || (s.tile & (s.tile - 1)) || s.tile > std::max(1, nrhs)) return false;
     if (fl == F64 && s.tile > 4) return false;
     if (s.block != 64 && s.block != 128 && s.block != 256) return false;
+    // a split wider than the RHS count only adds idle waves
+    int p2 = 1;
+    while (p2 < nrhs) p2 <<= 1;
+    if (s.tile * shape_rsplit(s) > p2) return false;
     return order_supported(geom, s.order, s.block);
 }
 
@@ -185,7 +193,7 @@ int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, con
         a.tile = sh.tile;
         a.block = sh.block;
         a.order = sh.order;
-        a.compressed = links_compressed(g, fl) ? 1 : 0;
+        a.compressed = links_compressed(g, fl);
         return launch_dslash(G, a, s);
     };
 
@@ -196,15 +204,16 @@ int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, con
     if ((rc = launch(ref_shape, ref.p))) return rc;
 
     std::vector<DslashShape> cands;
-    for (int tile : {1, 2, 4, 8, 16})
-        for (int block : {64, 128, 256})
-            for (int order : brick_orders(G, fi, tile)) {
-                DslashShape c;
-                c.tile = tile;
-                c.block = block;
-                c.order = order;
-                if (valid_shape(G, fl, nrhs, c)) cands.push_back(c);
-            }
+    for (int rsl = 0; rsl <= 2; ++rsl)  // RHS tiles of a site on 1, 2 or 4 waves
+        for (int tile : {1, 2, 4, 8, 16})
+            for (int block : {64, 128, 256})
+                for (int order : brick_orders(G, fi, tile << rsl)) {
+                    DslashShape c;
+                    c.tile = tile;
+                    c.block = block;
+                    c.order = order | rsl << 24;
+                    if (valid_shape(G, fl, nrhs, c)) cands.push_back(c);
+                }
 
     hipEvent_t e0, e1;
     HISQ_HIP_CHECK(hipEventCreate(&e0));

@@ -45,14 +45,19 @@ __device__ __forceinline__ bool finite(double v) { return v == v && fabs(v) <= 1
 __global__ void k_reduce_alpha(const double *__restrict__ part, int nb, CgState *st) {
     const int r = blockIdx.x;
     CgState &S = st[r];
-    if (S.flag != CG_RUNNING) return;
+    if (S.flag != CG_RUNNING) {
+        if (threadIdx.x == 0) S.xpend = 0;
+        return;
+    }
     const double pap = reduce_partials(part + (size_t)r * nb, nb);
     if (threadIdx.x == 0) {
         S.pap = pap;
         if (!(pap > 0.0) || !finite(pap)) {
             S.flag = CG_BREAKDOWN;
+            S.xpend = 0;
         } else {
             S.alpha = S.rho / pap;
+            S.xpend = 1;
         }
     }
 }
@@ -70,7 +75,7 @@ __global__ void k_reduce_beta(const double *__restrict__ part, int nb, CgState *
         S.since_ru += 1;
         if (!finite(rr)) {
             S.flag = CG_BREAKDOWN;
-        } else if (rr <= S.stop2 || (S.ru_period > 0 && S.since_ru >= S.ru_period)) {
+        } else if (rr <= S.stop2 || (S.ru_period > 0 && S.since_ru >= S.ru_period) || rr <= S.ru_delta2 * S.ru_rho) {
             S.flag = CG_ATTENTION;
         } else if (S.iter >= S.max_iter) {
             S.flag = CG_ATTENTION;
@@ -107,6 +112,7 @@ __global__ void k_reduce_true(const double *__restrict__ part, int nb, CgState *
             S.rho_new = rr;
             S.beta = rr / S.rho;
             S.rho = rr;
+            S.ru_rho = rr;
             S.flag = CG_RESUME;
         }
     }
@@ -120,6 +126,7 @@ __global__ void k_reduce_init(const double *__restrict__ part, int nb, CgState *
     if (threadIdx.x == 0) {
         S.true_rr = rr;
         S.rho = rr;
+        S.ru_rho = rr;
         if (!finite(rr)) {
             S.flag = CG_BREAKDOWN;
         } else if (rr <= S.true2) {
@@ -175,6 +182,75 @@ __global__ __launch_bounds__(256) void k_update_xr(Spinor<FX> x, Spinor<FR> r, S
     }
     const double s = block_sum(rr);
     if (threadIdx.x == 0) part[(size_t)i * nb + blockIdx.x] = s;
+}
+
+// r -= alpha q ; partial |r|^2   (running RHS)
+template <int FR, int FQ>
+__global__ __launch_bounds__(256) void k_update_r(Spinor<FR> r, Spinor<FQ> q, const CgState *__restrict__ st,
+                                                  double *__restrict__ part) {
+    const int i = blockIdx.y;
+    const int nb = gridDim.x;
+    if (st[i].flag != CG_RUNNING) return;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0;
+    if (h < r.vh) {
+        typedef RT<FR> R;
+        const R a = (R)st[i].alpha;
+        cx<R> rv[3];
+        cx<RT<FQ>> qv[3];
+        const Spinor<FR> Rr = r.rhs(i);
+        Rr.load(h, rv);
+        q.rhs(i).load(h, qv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            rv[c].re -= a * (R)qv[c].re;
+            rv[c].im -= a * (R)qv[c].im;
+            rr += (double)rv[c].re * (double)rv[c].re + (double)rv[c].im * (double)rv[c].im;
+        }
+        Rr.store(h, rv);
+    }
+    const double s = block_sum(rr);
+    if (threadIdx.x == 0) part[(size_t)i * nb + blockIdx.x] = s;
+}
+
+// x += alpha p (if this iteration's alpha is pending), then p = r + beta p
+// (if the RHS is still running): x, p and r read once
+template <int FX, int FR, int FP>
+__global__ __launch_bounds__(256) void k_update_xp(Spinor<FX> x, Spinor<FR> r, Spinor<FP> p,
+                                                   const CgState *__restrict__ st) {
+    const int i = blockIdx.y;
+    const bool upd_x = st[i].xpend != 0, upd_p = st[i].flag == CG_RUNNING;
+    if (!upd_x && !upd_p) return;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= p.vh) return;
+    typedef RT<FX> RX;
+    typedef RT<FP> RP;
+    cx<RP> pv[3];
+    const Spinor<FP> P = p.rhs(i);
+    P.load(h, pv);
+    if (upd_x) {
+        const RX a = (RX)st[i].alpha;
+        cx<RX> xv[3];
+        const Spinor<FX> X = x.rhs(i);
+        X.load(h, xv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xv[c].re += a * (RX)pv[c].re;
+            xv[c].im += a * (RX)pv[c].im;
+        }
+        X.store(h, xv);
+    }
+    if (upd_p) {
+        const RP b = (RP)st[i].beta;
+        cx<RT<FR>> rv[3];
+        r.rhs(i).load(h, rv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pv[c].re = (RP)rv[c].re + b * pv[c].re;
+            pv[c].im = (RP)rv[c].im + b * pv[c].im;
+        }
+        P.store(h, pv);
+    }
 }
 
 // p = r + beta p   (for RHS whose flag equals `when`)
@@ -318,6 +394,34 @@ void launch_update_xr(int fmt_sloppy, int vh, int n, void *x, void *r, const voi
         case F32: upd_xr<F32, F32, F32, F32>(vh, n, x, r, p, q, st, part, s); break;
         // FP16S sloppy: x, r, q kept in FP32, p (the Dslash input) in FP16S
         default: upd_xr<F32, F32, H16, F32>(vh, n, x, r, p, q, st, part, s); break;
+    }
+}
+
+void launch_update_r(int fmt_sloppy, int vh, int n, void *r, const void *q, const CgState *st, double *part,
+                     hipStream_t s) {
+    if (fmt_sloppy == F64)
+        hipLaunchKernelGGL((k_update_r<F64, F64>), site_grid(vh, n), dim3(256), 0, s, SPIN(F64, r), SPIN(F64, q), st,
+                           part);
+    else  // FP32 and FP16S sloppy: r and q in FP32
+        hipLaunchKernelGGL((k_update_r<F32, F32>), site_grid(vh, n), dim3(256), 0, s, SPIN(F32, r), SPIN(F32, q), st,
+                           part);
+}
+
+void launch_update_xp(int fmt_sloppy, int vh, int n, void *x, const void *r, void *p, const CgState *st,
+                      hipStream_t s) {
+    switch (fmt_sloppy) {
+        case F64:
+            hipLaunchKernelGGL((k_update_xp<F64, F64, F64>), site_grid(vh, n), dim3(256), 0, s, SPIN(F64, x),
+                               SPIN(F64, r), SPIN(F64, p), st);
+            break;
+        case F32:
+            hipLaunchKernelGGL((k_update_xp<F32, F32, F32>), site_grid(vh, n), dim3(256), 0, s, SPIN(F32, x),
+                               SPIN(F32, r), SPIN(F32, p), st);
+            break;
+        default:  // FP16S sloppy: x and r in FP32, p (the Dslash input) in FP16S
+            hipLaunchKernelGGL((k_update_xp<F32, F32, H16>), site_grid(vh, n), dim3(256), 0, s, SPIN(F32, x),
+                               SPIN(F32, r), SPIN(H16, p), st);
+            break;
     }
 }
 

@@ -64,6 +64,7 @@ static int check_params(const hisq_solver_params &p) {
     if (p.max_iter < 1) return fail(HISQ_ERR_INVALID, "max_iter must be >= 1");
     if (!valid_sloppy(p.sloppy_prec)) return fail(HISQ_ERR_INVALID, "bad sloppy_prec");
     if (p.graph_chunk < 0 || p.graph_chunk > 4096) return fail(HISQ_ERR_INVALID, "graph_chunk out of range");
+    if (!(p.ru_delta >= 0.0 && p.ru_delta < 1.0)) return fail(HISQ_ERR_INVALID, "ru_delta must be in [0, 1)");
     return HISQ_OK;
 }
 
@@ -103,6 +104,7 @@ void hisq_solver_params_default(hisq_solver_params *p) {
     p->warm_start = 0;
     p->fallback = 1;
     p->precond = nullptr;
+    p->ru_delta = 0.1;
 }
 
 int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, const double *lng,
@@ -127,25 +129,27 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
         return fail(HISQ_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
     DevBuf maxabs;
-    if ((rc = maxabs.alloc(sizeof(float)))) {
+    if ((rc = maxabs.alloc(2 * sizeof(float)))) {
         delete g;
         return rc;
     }
     if (!(prec_mask & HISQ_LINKS_FULL)) {
         // compress the long links when every one is unitary with det +-1
-        e = hipMemsetAsync(maxabs.p, 0, sizeof(float), s);
-        float defect = 1.f;
+        // (sign bits), or else when every one is a positive multiple of a
+        // unitary matrix (complex factor per link)
+        e = hipMemsetAsync(maxabs.p, 0, 2 * sizeof(float), s);
+        float defect[2] = {1.f, 1.f};
         if (e == hipSuccess) {
             launch_long_link_defect(g->geom, lng, (unsigned *)maxabs.p, s);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(&defect, maxabs.p, sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(defect, maxabs.p, 2 * sizeof(float), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             delete g;
             return fail(HISQ_ERR_HIP, std::string("long-link check: ") + hipGetErrorString(e));
         }
-        g->compressed = defect <= 1e-12f;
+        g->comp_mode = defect[0] <= 1e-12f ? COMP_SIGN : defect[1] <= 1e-12f ? COMP_KAPPA : COMP_NONE;
     }
     for (int f = 0; f < 3; ++f) {
         if (!(prec_mask & HISQ_PREC_MASK(f))) continue;
@@ -196,6 +200,21 @@ int hisq_gauge_create(hisq_gauge_t *out, const int dims[4], const double *fat, c
     return HISQ_OK;
 }
 
+int hisq_smear_links(const int dims[4], const double *thin, double *fat, double *lng, unsigned flags,
+                     void *stream) {
+    TraceRange tr_("hisq_smear_links");
+    int rc = check_dims(dims);
+    if (rc) return rc;
+    if (!thin || !fat || !lng) return fail(HISQ_ERR_INVALID, "thin, fat and lng are required");
+    if (flags & ~HISQ_SMEAR_ANTIPERIODIC_T) return fail(HISQ_ERR_INVALID, "unknown smearing flags");
+    if (!aligned16(thin) || !aligned16(fat) || !aligned16(lng))
+        return fail(HISQ_ERR_INVALID, "link fields must be 16-byte aligned");
+    const size_t n = (size_t)dims[0] * dims[1] * dims[2] * dims[3] * 4 * 9 * 16;
+    if (bytes_overlap(thin, n, fat, n) || bytes_overlap(thin, n, lng, n) || bytes_overlap(fat, n, lng, n))
+        return fail(HISQ_ERR_INVALID, "thin, fat and lng must not overlap");
+    return smear_links(dims, thin, fat, lng, flags, (hipStream_t)stream);
+}
+
 int hisq_gauge_destroy(hisq_gauge_t g) {
     if (!g) return HISQ_OK;
     (void)hipDeviceSynchronize();
@@ -206,7 +225,7 @@ int hisq_gauge_destroy(hisq_gauge_t g) {
 int hisq_gauge_links_compressed(hisq_gauge_t g) {
     int rc = check_handle(g);
     if (rc) return rc;
-    return g->compressed ? 1 : 0;
+    return g->comp_mode;
 }
 
 int hisq_gauge_device_bytes(hisq_gauge_t g, size_t *bytes) {
@@ -336,26 +355,19 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }
 
-// two host arrays of n doubles share memory (compared as addresses, since
-// the pointers need not belong to one array)
-static bool ranges_overlap(const double *a, const double *b, int n) {
-    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b, len = sizeof(double) * (uintptr_t)n;
-    return pa < pb + len && pb < pa + len;
-}
-
 // The coefficient outputs of the rational-approximation routines are written
 // one after another: none may share memory with another (alpha0 and delta are
 // single doubles, alpha and shift npole each).
 static int check_coefficient_outputs(int npole, const double *alpha0, const double *alpha, const double *shift,
                                      const double *delta) {
-    if (ranges_overlap(alpha, shift, npole)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
-    for (const double *arr : {alpha, shift}) {
-        if (ranges_overlap(alpha0, arr, 1) || ranges_overlap(arr, alpha0, npole))
-            return fail(HISQ_ERR_INVALID, "alpha0 must not overlap alpha or shift");
-        if (delta && (ranges_overlap(delta, arr, 1) || ranges_overlap(arr, delta, npole)))
+    const size_t one = sizeof(double), arr = sizeof(double) * (size_t)npole;
+    if (bytes_overlap(alpha, arr, shift, arr)) return fail(HISQ_ERR_INVALID, "alpha and shift must not overlap");
+    for (const double *a : {alpha, shift}) {
+        if (bytes_overlap(alpha0, one, a, arr)) return fail(HISQ_ERR_INVALID, "alpha0 must not overlap alpha or shift");
+        if (delta && bytes_overlap(delta, one, a, arr))
             return fail(HISQ_ERR_INVALID, "delta must not overlap alpha or shift");
     }
-    if (delta && ranges_overlap(delta, alpha0, 1)) return fail(HISQ_ERR_INVALID, "delta must not overlap alpha0");
+    if (delta && bytes_overlap(delta, one, alpha0, one)) return fail(HISQ_ERR_INVALID, "delta must not overlap alpha0");
     return HISQ_OK;
 }
 

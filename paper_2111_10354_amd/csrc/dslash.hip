@@ -32,7 +32,18 @@ Geom make_geom(const int dims[4]) {
     return g;
 }
 
-int dslash_grid_blocks(const Geom &g, int block) { return (g.vh + block - 1) / block; }
+// Bits 24-25 of a launch's `order`: log2 of the number of waves a site's RHS
+// tiles are split over (RS = 1, 2, 4).  A workgroup of `block` threads then
+// covers block / RS sites, and its RS waves of the same sites apply one RHS
+// tile each: they read the same link units (the later ones from the caches),
+// so each thread holds the accumulators and gathers of one tile only.
+static inline int order_rsplit(int order) { return 1 << ((order >> 24) & 3); }
+static inline int order_tiles(int order) { return order & 0xffffff; }
+
+int dslash_grid_blocks(const Geom &g, int block, int order) {
+    const int sb = block / order_rsplit(order);
+    return (g.vh + sb - 1) / sb;
+}
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -41,7 +52,7 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-template <int LF, int SI, int SO, int TILE, bool EPI, bool COMP>
+template <int LF, int SI, int SO, int TILE, bool EPI, int CM, int RS>
 __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restrict__ lptr, Spinor<SI> in,
                                                      Spinor<SO> out, Spinor<SI> y,
                                                      const double *__restrict__ diag,
@@ -50,15 +61,18 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                                                      int nrhs, int order) {
     typedef typename RealOf<LF>::T R;
     constexpr int G = LinkGroup<LF>::G;
+    constexpr bool NT = RS == 1;  // links read once per launch: stream them
     const int nb = gridDim.x;
     const int blk = blockIdx.x;
-    const int h = site_of_thread(g, blk, nb, (int)blockDim.x, threadIdx.x, order);
-    const int r0 = blockIdx.y * TILE;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rsub = wave % RS;  // this wave's RHS tile among the RS sharing its sites
+    const int h = site_of_thread(g, blk, nb, (int)blockDim.x / RS, (wave / RS) * 64 + lane, order & 0xffffff);
+    const int rb = blockIdx.y * RS * TILE;  // first RHS of the workgroup
+    const int r0 = rb + rsub * TILE;
     if (skip) {
         bool idle = true;
-#pragma unroll
-        for (int r = 0; r < TILE; ++r)
-            if (r0 + r < nrhs && skip[r0 + r].flag == CG_RUNNING) idle = false;
+        for (int r = rb; r < rb + RS * TILE && r < nrhs; ++r)
+            if (skip[r].flag == CG_RUNNING) idle = false;
         if (idle) return;  // uniform over the block
     }
 
@@ -66,7 +80,7 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
 #pragma unroll
     for (int r = 0; r < TILE; ++r) part[r] = 0.0;
 
-    if (h < g.vh) {
+    if (h < g.vh && r0 < nrhs) {
         const SiteCoord sc = decode_site(g, h, parity);
         cx<R> acc[TILE][3];
 #pragma unroll
@@ -97,8 +111,8 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
         // chunk) per loop trip with the gathers of all its RHS in flight
         // together; unrolled, the compiler hoists every gather of the site and
         // spills them to scratch.
-        if constexpr (!COMP) {
-            const Links<LF> links{lptr};
+        if constexpr (CM == COMP_NONE) {
+            const Links<LF, NT> links{lptr};
             auto group = [&](int gi) {
                 cx<R> w[9 * G];
                 links.load_group(gi, h, w);
@@ -113,10 +127,12 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                 for (int gi = 0; gi < 16 / G; ++gi) group(gi);
             }
         } else {
-            // fat slots whole; long slots from rows 0, 1 and the determinant sign
+            // fat slots whole; long slots from rows 0, 1 and the determinant
+            // sign (COMP_SIGN) or the complex factor kappa (COMP_KAPPA)
             constexpr int MC = CompGeom<LF>::MC, NC = CompGeom<LF>::NC;
-            const LinksC<LF> cl{lptr, g.vh};
-            const unsigned sg = cl.signs(h);
+            const LinksC<LF, CM, NT> cl{lptr, g.vh};
+            unsigned sg = 0;
+            if constexpr (CM == COMP_SIGN) sg = cl.signs(h);
             auto chunk = [&](int c) {
                 {
                     cx<R> w[18 * MC];
@@ -127,13 +143,16 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                 {
                     cx<R> lr[12 * MC];
                     cl.load_long(c, h, lr);
+                    cx<R> kap[2 * MC];
+                    if constexpr (CM == COMP_KAPPA) cl.load_kappa(c, h, kap);
 #pragma unroll
                     for (int s2 = 0; s2 < 2 * MC; ++s2) {
                         const int mu = c * MC + (s2 >> 1), bit = 2 * mu + (s2 & 1);
                         cx<R> m[9];
 #pragma unroll
                         for (int e = 0; e < 6; ++e) m[e] = lr[6 * s2 + e];
-                        rebuild_row2(m, ((sg >> bit) & 1u) ? R(-1) : R(1));
+                        if constexpr (CM == COMP_KAPPA) rebuild_row2(m, kap[s2]);
+                        else rebuild_row2(m, ((sg >> bit) & 1u) ? R(-1) : R(1));
                         apply(4 * mu + 2 + (s2 & 1), m);
                     }
                 }
@@ -182,40 +201,56 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
 
     if constexpr (EPI) {
         if (!partials) return;  // uniform: the caller wants no <y, out>
-        // deterministic block reduction: wave shuffles, then waves in order
+        // deterministic block reduction: wave shuffles, then the waves of each
+        // RHS tile in order
         __shared__ double red[4][TILE];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
         for (int r = 0; r < TILE; ++r) {
             double s = wave_sum(part[r]);
-            if (lane == 0) red[wv][r] = s;
+            if (lane == 0) red[wave][r] = s;
         }
         __syncthreads();
-        if (threadIdx.x < TILE && r0 + (int)threadIdx.x < nrhs) {
-            const int r = threadIdx.x;
+        const int t = threadIdx.x;
+        if (t < RS * TILE && rb + t < nrhs) {
+            const int rs = t / TILE, r = t % TILE;
             double s = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][r];
-            partials[(size_t)(r0 + r) * nb + blk] = s;
+            for (int w = rs; w < (int)(blockDim.x >> 6); w += RS) s += red[w][r];
+            partials[(size_t)(rb + t) * nb + blk] = s;
         }
     }
 }
 
-template <int LF, int SI, int SO, int TILE, bool EPI>
-static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+template <int LF, int SI, int SO, int TILE, bool EPI, int RS>
+static void launch_rs(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     dim3 block(a.block);
-    dim3 grid(dslash_grid_blocks(g, a.block), (a.nrhs + TILE - 1) / TILE);
+    const int ntiles = (a.nrhs + TILE - 1) / TILE;
+    dim3 grid(dslash_grid_blocks(g, a.block, a.order), (ntiles + RS - 1) / RS);
     Spinor<SI> in = spinor_view<SI>(const_cast<void *>(a.in), g.vh);
     Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
     Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);
     if constexpr (LF != F64) {  // FP64 links are always stored whole
-        if (a.compressed) {
-            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, true>), grid, block, 0, s, g, a.links, in, out,
-                               y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+        if (a.compressed == COMP_SIGN) {
+            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_SIGN, RS>), grid, block, 0, s, g, a.links,
+                               in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+            return;
+        }
+        if (a.compressed == COMP_KAPPA) {
+            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_KAPPA, RS>), grid, block, 0, s, g, a.links,
+                               in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
             return;
         }
     }
-        hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, false>), grid, block, 0, s, g, a.links, in, out, y,
-                           a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+    hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_NONE, RS>), grid, block, 0, s, g, a.links, in, out,
+                       y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+}
+
+template <int LF, int SI, int SO, int TILE, bool EPI>
+static void launch_one(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+    switch (order_rsplit(a.order)) {
+        case 2: launch_rs<LF, SI, SO, TILE, EPI, 2>(g, a, s); break;
+        case 4: launch_rs<LF, SI, SO, TILE, EPI, 4>(g, a, s); break;
+        default: launch_rs<LF, SI, SO, TILE, EPI, 1>(g, a, s); break;
+    }
 }
 
 template <int LF, int SI, int SO, bool EPI>
@@ -248,8 +283,12 @@ static int launch_epi(const Geom &g, const DslashLaunch &a, hipStream_t s) {
 }
 
 bool order_supported(const Geom &g, int order, int block) {
+    if (order < 0 || (order >> 26)) return false;
+    const int rs = order_rsplit(order);
+    if (rs == 8 || block / rs < 64) return false;  // whole waves of sites
+    block /= rs;
+    order = order_tiles(order);
     const int kind = order & 0xff;
-    if (order < 0) return false;
     if (kind == 0) return order == 0;
     if (g.vh % 64 || (g.lxh * g.L[1]) % 64) return false;
     if (kind == 1) return order == 1;

@@ -352,7 +352,7 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
     static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
     FcgState hs;
     std::memset(&hs, 0, sizeof(hs));
-    hs.cg.stop2 = prm.tol * prm.tol * b2;  // iterated-residual trigger (tightened below)
+    hs.cg.stop2 = kResidualMargin * kResidualMargin * prm.tol * prm.tol * b2;  // iterated-residual trigger (tightened below)
     hs.cg.true2 = hs.cg.stop2;             // target of the true residual
     hs.cg.ru_period = std::max(1, prm.ru_period);
     hs.cg.max_iter = prm.max_iter;
@@ -464,10 +464,10 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
         stats->true_residual = rel;
         stats->wall_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         stats->dslash_bytes =
-            (double)fcg_iters * (double)(dslash_algorithmic_bytes(F32, F32, F32, vh, 1, false, g->compressed) +
-                                         dslash_algorithmic_bytes(F32, F32, F32, vh, 1, true, g->compressed)) +
-            (double)(fcg_ru + 1) * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
-                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed)) +
+            (double)fcg_iters * (double)(dslash_algorithmic_bytes(F32, F32, F32, vh, 1, false, g->comp_mode) +
+                                         dslash_algorithmic_bytes(F32, F32, F32, vh, 1, true, g->comp_mode)) +
+            (double)(fcg_ru + 1) * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->comp_mode) +
+                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->comp_mode)) +
             cg_st.dslash_bytes;
     }
     return status;

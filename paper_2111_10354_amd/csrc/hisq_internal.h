@@ -254,37 +254,55 @@ template <> struct LinkGroup<H16> { static constexpr int G = 4; };
 
 inline int link_group_size(int f) { return f == F64 ? 1 : f == F32 ? 2 : 4; }
 
-// Compressed layout (the gauge-field compression of the D-slash: only part of
-// a link is stored and the rest recomputed from its unitarity).  Used when
-// every long link is unitary with determinant +1 or -1: slots j = 2, 3 keep
-// rows 0 and 1, and row 2 = det * conj(row 0 x row 1) is rebuilt in the
-// kernel; the fat links (not unitary in general) stay whole.  The sites of a
-// 64-site tile are stored chunk by chunk; chunk c covers MC directions
+// Compressed layouts (the gauge-field compression of the D-slash: only part of
+// a link is stored and the rest recomputed from its unitarity).  Slots
+// j = 2, 3 (long links) keep rows 0 and 1; row 2 is rebuilt in the kernel as
+// kappa * conj(row 0 x row 1), which holds for every multiple M = s U of a
+// unitary U (s > 0) with kappa = det(M) / s^4.  Two modes:
+//   COMP_SIGN  kappa = +-1 (unitary links with determinant +-1, e.g. products
+//              of SU(3) links with the staggered signs folded in), one bit
+//              per slot in a 32-bit word per site after the last tile;
+//   COMP_KAPPA kappa complex (any multiple of a U(3) link, e.g. the HISQ
+//              Naik links -W W W / 24 of U(3)-projected W), stored per slot
+//              in one extra 16-byte unit per chunk.
+// The fat links (not unitary in general) stay whole.  The sites of a 64-site
+// tile are stored chunk by chunk; chunk c covers MC directions
 // mu = c MC .. c MC + MC - 1 and holds first the fat slots (mu, j = 0, 1 for
-// each mu of the chunk, 9 complex entries each) and then the long slots
-// (mu, j = 2, 3, rows 0 and 1 = 6 complex entries each), entries row-major,
-// slots in that order, packed into 16-byte units:
-//   byte offset of (site h, chunk c, unit e) = (((h / 64) * NC + c) * UC + e) * 1024 + (h % 64) * 16
+// each mu of the chunk, 9 complex entries each), then the long slots (mu,
+// j = 2, 3, rows 0 and 1 = 6 complex entries each), entries row-major, slots
+// in that order, packed into 16-byte units, and in COMP_KAPPA mode one unit of
+// the chunk's 2 MC kappas (slot order):
+//   byte offset of (site h, chunk c, unit e) = (((h / 64) * NC + c) * UC + e) * 1024 + (h % 64) * 16,
+//   UC = UF + UL (+ 1 in COMP_KAPPA mode)
 //   FP64: MC 1, NC 4, 18 fat + 12 long units;  FP32: MC 1, NC 4, 9 + 6;  FP16: MC 2, NC 2, 9 + 6.
-// After the last tile, one 32-bit word per site holds the determinant signs:
-// bit 2 mu + (j - 2) set when the determinant of slot (mu, j) is -1.
+// COMP_SIGN: after the last tile, one 32-bit word per site holds the
+// determinant signs: bit 2 mu + (j - 2) set when the determinant of slot
+// (mu, j) is -1.
+enum CompMode { COMP_NONE = 0, COMP_SIGN = 1, COMP_KAPPA = 2 };
 template <int F> struct CompGeom { static constexpr int MC = 1, NC = 4, UF = 18, UL = 12; };
 template <> struct CompGeom<F32> { static constexpr int MC = 1, NC = 4, UF = 9, UL = 6; };
 template <> struct CompGeom<H16> { static constexpr int MC = 2, NC = 2, UF = 9, UL = 6; };
-// 16-byte units per site (per 64-site tile, in units of 1 KiB) = NC * (UF + UL)
+// 16-byte units per chunk and per site (per 64-site tile, in units of 1 KiB)
 template <int F>
-__host__ __device__ constexpr int comp_units() {
-    return CompGeom<F>::NC * (CompGeom<F>::UF + CompGeom<F>::UL);
+__host__ __device__ constexpr int comp_chunk_units(int mode) {
+    return CompGeom<F>::UF + CompGeom<F>::UL + (mode == COMP_KAPPA ? 1 : 0);
 }
-__host__ __device__ inline int comp_units_per_site(int f) {
-    return f == F64 ? comp_units<F64>() : f == F32 ? comp_units<F32>() : comp_units<H16>();
+template <int F>
+__host__ __device__ constexpr int comp_units(int mode = COMP_SIGN) {
+    return CompGeom<F>::NC * comp_chunk_units<F>(mode);
+}
+__host__ __device__ inline int comp_units_per_site(int f, int mode = COMP_SIGN) {
+    return f == F64 ? comp_units<F64>(mode) : f == F32 ? comp_units<F32>(mode) : comp_units<H16>(mode);
 }
 static_assert(comp_units<F64>() == 120 && comp_units<F32>() == 60 && comp_units<H16>() == 30,
               "compressed layouts: 15 or 30 units per direction chunk");
+static_assert(comp_units<F32>(COMP_KAPPA) == 64 && comp_units<H16>(COMP_KAPPA) == 32,
+              "kappa layouts: one extra unit per chunk");
 
-inline size_t link_parity_bytes(int f, int64_t vh, bool compressed = false) {
+inline size_t link_parity_bytes(int f, int64_t vh, int mode = COMP_NONE) {
     const int64_t tiles = (vh + LINK_TILE - 1) / LINK_TILE;
-    if (compressed) return (size_t)tiles * (comp_units_per_site(f) * 1024 + LINK_TILE * 4);
+    if (mode == COMP_SIGN) return (size_t)tiles * (comp_units_per_site(f, mode) * 1024 + LINK_TILE * 4);
+    if (mode == COMP_KAPPA) return (size_t)tiles * comp_units_per_site(f, mode) * 1024;
     return (size_t)tiles * (16 / link_group_size(f)) * 9 * 1024;
 }
 
@@ -292,36 +310,45 @@ __host__ __device__ __forceinline__ const u4v *link_unit_ptr(const void *base, i
     return (const u4v *)base + ((size_t)((h >> 6) * ng + gi) * 9) * 64 + (h & 63);
 }
 
-template <int F> struct Links;
+// Link loads: non-temporal (streamed past the caches) when each link byte is
+// read once per launch; cached when several waves of a workgroup read the same
+// links (the RHS of a site split over waves).
+template <bool NT, class T>
+__device__ __forceinline__ T ldlink(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
-template <> struct Links<F64> {
+template <int F, bool NT = true> struct Links;
+
+template <bool NT> struct Links<F64, NT> {
     const void *p;
     // the G*9 = 9 complex entries of group gi (= slot gi)
     __device__ __forceinline__ void load_group(int gi, int h, cx<double> w[9]) const {
         const u4v *b = link_unit_ptr(p, 16, gi, h);
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            d2v a = __builtin_bit_cast(d2v, __builtin_nontemporal_load(b + e * 64));
+            d2v a = __builtin_bit_cast(d2v, ldlink<NT>(b + e * 64));
             w[e] = {a.x, a.y};
         }
     }
 };
 
-template <> struct Links<F32> {
+template <bool NT> struct Links<F32, NT> {
     const void *p;
     // 18 complex entries: slots 2 gi and 2 gi + 1
     __device__ __forceinline__ void load_group(int gi, int h, cx<float> w[18]) const {
         const u4v *b = link_unit_ptr(p, 8, gi, h);
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            f4v a = __builtin_bit_cast(f4v, __builtin_nontemporal_load(b + e * 64));
+            f4v a = __builtin_bit_cast(f4v, ldlink<NT>(b + e * 64));
             w[2 * e] = {a.x, a.y};
             w[2 * e + 1] = {a.z, a.w};
         }
     }
 };
 
-template <> struct Links<H16> {
+template <bool NT> struct Links<H16, NT> {
     const void *p;
     // 36 complex entries: slots 4 gi .. 4 gi + 3
     __device__ __forceinline__ void load_group(int gi, int h, cx<float> w[36]) const {
@@ -330,102 +357,113 @@ template <> struct Links<H16> {
         for (int e = 0; e < 9; ++e) {
             // reinterpret all 16 bytes at once: bit-casting a single element
             // of the loaded vector (a[q]) was compiled as if q were 0
-            const h8v a = __builtin_bit_cast(h8v, __builtin_nontemporal_load(b + e * 64));
+            const h8v a = __builtin_bit_cast(h8v, ldlink<NT>(b + e * 64));
 #pragma unroll
             for (int q = 0; q < 4; ++q) w[4 * e + q] = {(float)a[2 * q], (float)a[2 * q + 1]};
         }
     }
 };
 
-// Loaders of the compressed layout: fat part (2 MC slots, 9 entries each) and
-// long part (2 MC slots, rows 0 and 1 = 6 entries each) of chunk c.
-template <int F> struct LinksC;
+// Loaders of the compressed layouts: fat part (2 MC slots, 9 entries each),
+// long part (2 MC slots, rows 0 and 1 = 6 entries each) and, in COMP_KAPPA
+// mode, the 2 MC kappas of chunk c.
+template <int F, int CM, bool NT = true> struct LinksC;
 
-template <int F>
+template <int F, int CM>
 __host__ __device__ __forceinline__ const u4v *comp_unit_ptr(const void *base, int c, int h) {
-    constexpr int NC = CompGeom<F>::NC, UC = CompGeom<F>::UF + CompGeom<F>::UL;
+    constexpr int NC = CompGeom<F>::NC, UC = comp_chunk_units<F>(CM);
     return (const u4v *)base + ((size_t)((h >> 6) * NC + c) * UC) * 64 + (h & 63);
 }
 
 template <int F>
 __device__ __forceinline__ unsigned comp_signs(const void *base, int vh, int h) {
     const size_t tiles = (size_t)(vh + LINK_TILE - 1) / LINK_TILE;
-    const unsigned *sg = (const unsigned *)((const char *)base + tiles * comp_units_per_site(F) * 1024);
+    const unsigned *sg = (const unsigned *)((const char *)base + tiles * comp_units_per_site(F, COMP_SIGN) * 1024);
     return __builtin_nontemporal_load(sg + h);
 }
 
-template <> struct LinksC<F64> {
+template <int CM, bool NT> struct LinksC<F64, CM, NT> {
     const void *p;
     int vh;
     __device__ __forceinline__ unsigned signs(int h) const { return comp_signs<F64>(p, vh, h); }
     __device__ __forceinline__ void load_fat(int c, int h, cx<double> w[18]) const {
-        const u4v *b = comp_unit_ptr<F64>(p, c, h);
+        const u4v *b = comp_unit_ptr<F64, CM>(p, c, h);
 #pragma unroll
         for (int e = 0; e < 18; ++e) {
-            d2v a = __builtin_bit_cast(d2v, __builtin_nontemporal_load(b + e * 64));
+            d2v a = __builtin_bit_cast(d2v, ldlink<NT>(b + e * 64));
             w[e] = {a.x, a.y};
         }
     }
     __device__ __forceinline__ void load_long(int c, int h, cx<double> r[12]) const {
-        const u4v *b = comp_unit_ptr<F64>(p, c, h) + 18 * 64;
+        const u4v *b = comp_unit_ptr<F64, CM>(p, c, h) + 18 * 64;
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
-            d2v a = __builtin_bit_cast(d2v, __builtin_nontemporal_load(b + e * 64));
+            d2v a = __builtin_bit_cast(d2v, ldlink<NT>(b + e * 64));
             r[e] = {a.x, a.y};
         }
     }
 };
 
-template <> struct LinksC<F32> {
+template <int CM, bool NT> struct LinksC<F32, CM, NT> {
     const void *p;
     int vh;
     __device__ __forceinline__ unsigned signs(int h) const { return comp_signs<F32>(p, vh, h); }
     __device__ __forceinline__ void load_fat(int c, int h, cx<float> w[18]) const {
-        const u4v *b = comp_unit_ptr<F32>(p, c, h);
+        const u4v *b = comp_unit_ptr<F32, CM>(p, c, h);
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            f4v a = __builtin_bit_cast(f4v, __builtin_nontemporal_load(b + e * 64));
+            f4v a = __builtin_bit_cast(f4v, ldlink<NT>(b + e * 64));
             w[2 * e] = {a.x, a.y};
             w[2 * e + 1] = {a.z, a.w};
         }
     }
     __device__ __forceinline__ void load_long(int c, int h, cx<float> r[12]) const {
-        const u4v *b = comp_unit_ptr<F32>(p, c, h) + 9 * 64;
+        const u4v *b = comp_unit_ptr<F32, CM>(p, c, h) + 9 * 64;
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-            f4v a = __builtin_bit_cast(f4v, __builtin_nontemporal_load(b + e * 64));
+            f4v a = __builtin_bit_cast(f4v, ldlink<NT>(b + e * 64));
             r[2 * e] = {a.x, a.y};
             r[2 * e + 1] = {a.z, a.w};
         }
     }
+    __device__ __forceinline__ void load_kappa(int c, int h, cx<float> k[2]) const {
+        const f4v a = __builtin_bit_cast(f4v, ldlink<NT>(comp_unit_ptr<F32, CM>(p, c, h) + 15 * 64));
+        k[0] = {a.x, a.y};
+        k[1] = {a.z, a.w};
+    }
 };
 
-template <> struct LinksC<H16> {
+template <int CM, bool NT> struct LinksC<H16, CM, NT> {
     const void *p;
     int vh;
     __device__ __forceinline__ unsigned signs(int h) const { return comp_signs<H16>(p, vh, h); }
     __device__ __forceinline__ void load_fat(int c, int h, cx<float> w[36]) const {
-        const u4v *b = comp_unit_ptr<H16>(p, c, h);
+        const u4v *b = comp_unit_ptr<H16, CM>(p, c, h);
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
-            const h8v a = __builtin_bit_cast(h8v, __builtin_nontemporal_load(b + e * 64));
+            const h8v a = __builtin_bit_cast(h8v, ldlink<NT>(b + e * 64));
 #pragma unroll
             for (int q = 0; q < 4; ++q) w[4 * e + q] = {(float)a[2 * q], (float)a[2 * q + 1]};
         }
     }
     __device__ __forceinline__ void load_long(int c, int h, cx<float> r[24]) const {
-        const u4v *b = comp_unit_ptr<H16>(p, c, h) + 9 * 64;
+        const u4v *b = comp_unit_ptr<H16, CM>(p, c, h) + 9 * 64;
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-            const h8v a = __builtin_bit_cast(h8v, __builtin_nontemporal_load(b + e * 64));
+            const h8v a = __builtin_bit_cast(h8v, ldlink<NT>(b + e * 64));
 #pragma unroll
             for (int q = 0; q < 4; ++q) r[4 * e + q] = {(float)a[2 * q], (float)a[2 * q + 1]};
         }
     }
+    __device__ __forceinline__ void load_kappa(int c, int h, cx<float> k[4]) const {
+        const h8v a = __builtin_bit_cast(h8v, ldlink<NT>(comp_unit_ptr<H16, CM>(p, c, h) + 15 * 64));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) k[q] = {(float)a[2 * q], (float)a[2 * q + 1]};
+    }
 };
 
-// Row 2 of a unitary matrix with determinant d = +-1 from rows 0 and 1:
-// m[6..8] = d * conj(row0 x row1).
+// Row 2 of a multiple of a unitary matrix from rows 0 and 1:
+// m[6..8] = kappa * conj(row0 x row1) with kappa = +-1 (real d) or complex.
 template <class R>
 __device__ __forceinline__ void rebuild_row2(cx<R> m[9], R d) {
     const cx<R> *a = m, *b = m + 3;
@@ -435,6 +473,16 @@ __device__ __forceinline__ void rebuild_row2(cx<R> m[9], R d) {
     m[6] = {d * (c0.re - c1.re), -d * (c0.im - c1.im)};
     m[7] = {d * (c2.re - c3.re), -d * (c2.im - c3.im)};
     m[8] = {d * (c4.re - c5.re), -d * (c4.im - c5.im)};
+}
+template <class R>
+__device__ __forceinline__ void rebuild_row2(cx<R> m[9], cx<R> k) {
+    const cx<R> *a = m, *b = m + 3;
+    const cx<R> c0 = cmul(a[1], b[2]), c1 = cmul(a[2], b[1]);
+    const cx<R> c2 = cmul(a[2], b[0]), c3 = cmul(a[0], b[2]);
+    const cx<R> c4 = cmul(a[0], b[1]), c5 = cmul(a[1], b[0]);
+    m[6] = cmul(k, cx<R>{c0.re - c1.re, c1.im - c0.im});
+    m[7] = cmul(k, cx<R>{c2.re - c3.re, c3.im - c2.im});
+    m[8] = cmul(k, cx<R>{c4.re - c5.re, c5.im - c4.im});
 }
 
 // ------------------------------------------------------------------ tracing
@@ -463,10 +511,12 @@ const char *get_error();
 // ------------------------------------------------------------------ launch wrappers
 // Link packing: canonical [V][4][3][3] complex double -> packed per parity.
 int launch_pack_links(const Geom &g, int fmt, const double *fat, const double *lng, void *dst_even,
-                      void *dst_odd, float *maxabs_dev, bool compressed, hipStream_t s);
+                      void *dst_odd, float *maxabs_dev, int comp_mode, hipStream_t s);
 // Largest deviation of any long link from a unitary matrix with determinant
-// +-1 (max |L L^+ - 1| entry or | det - round(det) |), into *defect_bits as
-// float bits (atomic max; zero it first).
+// +-1 (max |L L^+ - 1| entry or | det - round(det) |) into defect_bits[0], and
+// from a positive multiple s U of a unitary U (max |L L^+ - s^2| entry / s^2,
+// s^2 = tr(L L^+) / 3) into defect_bits[1], as float bits (atomic max; zero
+// both first).
 void launch_long_link_defect(const Geom &g, const double *lng, unsigned *defect_bits, hipStream_t s);
 
 struct CgState;
@@ -488,11 +538,14 @@ struct DslashLaunch {
     int tile;
     int block;
     int order;  // tile processing order: 0 memory order, 1 t-fastest planes,
-                // 2 | BY << 8 | BZ << 16 XCD bricks (dslash.hip)
-    int compressed;  // links in the compressed layout
+                // 2 | BY << 8 | BZ << 16 XCD bricks (dslash.hip); bits 24-25:
+                // log2 of the waves a site's RHS tiles are split over
+    int compressed;  // links in a compressed layout (CompMode)
 };
 int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s);
 bool order_supported(const Geom &g, int order, int block);
-int dslash_grid_blocks(const Geom &g, int block);
+// Workgroups along the sites of a launch with `block` threads and tile order
+// `order` (bits 24-25: the RHS split over waves).
+int dslash_grid_blocks(const Geom &g, int block, int order);
 
 }  // namespace hisq

@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "solver_internal.h"
@@ -52,10 +54,10 @@ __global__ void k_ms_alpha(const CgState *__restrict__ base, MsState *ms, MsGlob
     S.pending = 1;
 }
 
-// after beta: beta_k, roll the zetas, convergence of each shift
-__global__ void k_ms_beta(const CgState *__restrict__ base, MsState *ms, MsGlobal *gl, int nshift) {
+// after beta: beta_k, roll the zetas, convergence of each shift (base flag == when)
+__global__ void k_ms_beta(const CgState *__restrict__ base, MsState *ms, MsGlobal *gl, int nshift, int when) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (base->flag != CG_RUNNING) return;
+    if (base->flag != when) return;
     if (k < nshift && k > 0) {
         MsState &S = ms[k];
         if (S.active) {
@@ -75,72 +77,289 @@ __global__ void k_ms_beta(const CgState *__restrict__ base, MsState *ms, MsGloba
 }
 
 // x_k += alpha_k p_k ; p_k = zeta_k r + beta_k p_k   for every active shift, r read once
-__global__ __launch_bounds__(256) void k_ms_update(Spinor<F64> x, Spinor<F64> p, Spinor<F64> r,
+template <int F>
+__global__ __launch_bounds__(256) void k_ms_update(Spinor<F> x, Spinor<F> p, Spinor<F> r,
                                                    const CgState *__restrict__ base, MsState *ms,
-                                                   int nshift) {
-    if (base->flag != CG_RUNNING) return;
+                                                   int nshift, int when) {
+    if (base->flag != when) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= r.vh) return;
-    cx<double> rv[3];
+    typedef typename RealOf<F>::T R;
+    cx<R> rv[3];
     r.load(h, rv);
     for (int k = 1; k < nshift; ++k) {
         const MsState &S = ms[k];
         if (!S.active) continue;
-        cx<double> xv[3], pv[3];
-        const Spinor<F64> X = x.rhs(k), P = p.rhs(k);
+        const R a = (R)S.alpha, z = (R)S.zeta, bk = (R)S.beta;
+        cx<R> xv[3], pv[3];
+        const Spinor<F> X = x.rhs(k), P = p.rhs(k);
         X.load(h, xv);
         P.load(h, pv);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            xv[c].re += S.alpha * pv[c].re;
-            xv[c].im += S.alpha * pv[c].im;
-            pv[c].re = S.zeta * rv[c].re + S.beta * pv[c].re;
-            pv[c].im = S.zeta * rv[c].im + S.beta * pv[c].im;
+            xv[c].re += a * pv[c].re;
+            xv[c].im += a * pv[c].im;
+            pv[c].re = z * rv[c].re + bk * pv[c].re;
+            pv[c].im = z * rv[c].im + bk * pv[c].im;
         }
         X.store(h, xv);
         P.store(h, pv);
     }
 }
 
-__global__ void k_ms_clear_pending(const CgState *__restrict__ base, MsState *ms, int nshift) {
+__global__ void k_ms_clear_pending(const CgState *__restrict__ base, MsState *ms, int nshift, int when) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (base->flag != CG_RUNNING || k >= nshift) return;
+    if (base->flag != when || k >= nshift) return;
     ms[k].pending = 0;
 }
 
 // final x_k += alpha_k p_k for shifts whose last update is still pending
-__global__ __launch_bounds__(256) void k_ms_flush(Spinor<F64> x, Spinor<F64> p, const MsState *ms,
-                                                  int nshift) {
+template <int F>
+__global__ __launch_bounds__(256) void k_ms_flush(Spinor<F> x, Spinor<F> p, const MsState *ms, int nshift) {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= x.vh) return;
+    typedef typename RealOf<F>::T R;
     for (int k = 1; k < nshift; ++k) {
         const MsState &S = ms[k];
         if (!S.pending) continue;
-        cx<double> xv[3], pv[3];
-        const Spinor<F64> X = x.rhs(k);
+        const R a = (R)S.alpha;
+        cx<R> xv[3], pv[3];
+        const Spinor<F> X = x.rhs(k);
         X.load(h, xv);
         p.rhs(k).load(h, pv);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            xv[c].re += S.alpha * pv[c].re;
-            xv[c].im += S.alpha * pv[c].im;
+            xv[c].re += a * pv[c].re;
+            xv[c].im += a * pv[c].im;
         }
         X.store(h, xv);
     }
 }
 
-// b replicated into every slot of a stack
-__global__ __launch_bounds__(256) void k_replicate(Spinor<F64> src, Spinor<F64> dst) {
+// b (FP64) replicated into every slot of a stack of format F
+template <int F>
+__global__ __launch_bounds__(256) void k_replicate(Spinor<F64> src, Spinor<F> dst) {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= src.vh) return;
+    typedef typename RealOf<F>::T R;
     cx<double> v[3];
     src.load(h, v);
-    dst.rhs(blockIdx.y).store(h, v);
+    cx<R> w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = {(R)v[c].re, (R)v[c].im};
+    dst.rhs(blockIdx.y).store(h, w);
 }
 
 struct MsWorkspace {
     DevBuf t, q, r, p0, pk, part, state, ms, gl, diag, bstack;
 };
+
+// Mixed-precision multi-shift CG.  The Krylov iteration runs with FP32 links
+// and vectors: base residual and direction, every shifted direction and
+// solution.  The base solution is accumulated in FP64 with reliable updates
+// (x_hi += x_sloppy, r = b - (A + sigma_0) x_hi in FP64, every ru_period
+// iterations and whenever the iterated residual claims convergence); after
+// such an update the recurrences continue from the recomputed residual, with
+// each shifted residual taken as zeta_k times it.  The shifted residuals are
+// collinear with the base residual only up to the rounding of the FP32
+// operator, so the shifted solutions stall at a relative residual of order
+// 1e-6; the batched mixed-precision CG warm-started from them finishes every
+// shift on its own FP64 true residual.
+static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int ns, const int *order, const double *shifts,
+                                  const double *b, double *x, const hisq_solver_params &prm,
+                                  hisq_solver_stats *stats, hipStream_t s) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const int vh = g->geom.vh;
+    if (!g->links[F32][0].p) {
+        set_error("multishift: mixed precision needs packed FP32 links in the handle");
+        return HISQ_ERR_UNSUPPORTED;
+    }
+    const double sig0 = shifts[order[0]];
+    const size_t s64 = spinor_bytes(F64, vh), s32 = spinor_bytes(F32, vh);
+    const int nb = blas_blocks(vh);
+    DevBuf r32, t32, q32, p32, x32, x64, t64, ax64, r64, part, state, msb, glb, diag, scal, bstack;
+    int rc;
+    if ((rc = r32.alloc(s32)) || (rc = t32.alloc(s32)) || (rc = q32.alloc(s32)) || (rc = p32.alloc(s32 * ns)) ||
+        (rc = x32.alloc(s32 * ns)) || (rc = x64.alloc(s64 * ns)) || (rc = t64.alloc(s64)) ||
+        (rc = ax64.alloc(s64)) || (rc = r64.alloc(s64)) ||
+        (rc = part.alloc(sizeof(double) * std::max((vh + 63) / 64, nb))) || (rc = state.alloc(sizeof(CgState))) ||
+        (rc = msb.alloc(sizeof(MsState) * ns)) || (rc = glb.alloc(sizeof(MsGlobal))) ||
+        (rc = diag.alloc(sizeof(double))) || (rc = scal.alloc(sizeof(double))) || (rc = bstack.alloc(s64 * ns)))
+        return rc;
+    CgState *base = (CgState *)state.p;
+    MsState *ms = (MsState *)msb.p;
+    MsGlobal *gl = (MsGlobal *)glb.p;
+    double *pt = (double *)part.p;
+    const Spinor<F32> X = spinor_view<F32>(x32.p, vh), P = spinor_view<F32>(p32.p, vh);
+    const Spinor<F32> Rv = spinor_view<F32>(r32.p, vh);
+    void *p0 = p32.p;  // base direction: slot 0 of the direction stack
+    void *xhi = x64.p;  // base FP64 solution: slot 0 of the FP64 solution stack
+
+    const double diag0 = 4.0 * mass * mass + sig0;
+    HISQ_HIP_CHECK(hipMemcpyAsync(diag.p, &diag0, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_norm2(vh, 1, b, pt, s);
+    launch_reduce(RED_STORE, 1, pt, nb, nullptr, (double *)scal.p, s);
+    double b2 = 0;
+    HISQ_HIP_CHECK(hipMemcpyAsync(&b2, scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HISQ_HIP_CHECK(hipStreamSynchronize(s));
+
+    CgState hb;
+    std::memset(&hb, 0, sizeof(hb));
+    hb.stop2 = kResidualMargin * kResidualMargin * prm.tol * prm.tol * b2;
+    hb.true2 = hb.stop2;
+    hb.ru_period = std::max(1, prm.ru_period);
+    hb.ru_delta2 = prm.ru_delta * prm.ru_delta;
+    hb.max_iter = prm.max_iter;
+    hb.flag = CG_ATTENTION;
+    std::vector<MsState> hm(ns);
+    for (int k = 0; k < ns; ++k) {
+        std::memset(&hm[k], 0, sizeof(MsState));
+        hm[k].delta = shifts[order[k]] - sig0;
+        hm[k].zeta = hm[k].zeta_old = hm[k].zeta_new = 1.0;
+        hm[k].active = 1;
+    }
+    MsGlobal hg{1.0, 0.0, prm.tol * std::sqrt(b2)};
+    HISQ_HIP_CHECK(hipMemcpyAsync(base, &hb, sizeof(hb), hipMemcpyHostToDevice, s));
+    HISQ_HIP_CHECK(hipMemcpyAsync(ms, hm.data(), sizeof(MsState) * ns, hipMemcpyHostToDevice, s));
+    HISQ_HIP_CHECK(hipMemcpyAsync(gl, &hg, sizeof(hg), hipMemcpyHostToDevice, s));
+
+    // r = b, p = p_k = b, x_k = 0, x_hi = 0
+    launch_convert(F64, F32, vh, 1, b, r32.p, nullptr, -1, s);
+    launch_norm2(vh, 1, b, pt, s);
+    launch_reduce(RED_INIT, 1, pt, nb, base, nullptr, s);
+    launch_zero(F32, vh, ns, x32.p, s);
+    launch_zero(F64, vh, 1, xhi, s);
+    const dim3 rep_grid((vh + 255) / 256, ns);
+    hipLaunchKernelGGL(k_replicate<F32>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), P);
+    HISQ_HIP_CHECK(hipGetLastError());
+
+    const int tb = 64, gb = (ns + tb - 1) / tb;
+    const dim3 beta_block(std::max(64, ((ns + 63) / 64) * 64));
+    auto iteration = [&](hipStream_t st) -> int {
+        int r2;
+        if ((r2 = gauge_dslash(g, 1, F32, F32, F32, 1, p0, t32.p, nullptr, nullptr, nullptr, base, st))) return r2;
+        if ((r2 = gauge_dslash(g, 0, F32, F32, F32, 1, t32.p, q32.p, p0, (const double *)diag.p, pt, base, st)))
+            return r2;
+        launch_reduce(RED_ALPHA, 1, pt, nb_dslash(g, F32, F32, F32, 1, true), base, nullptr, st);
+        hipLaunchKernelGGL(k_ms_alpha, dim3(gb), dim3(tb), 0, st, base, ms, gl, ns);
+        launch_update_xr(F32, vh, 1, x32.p, r32.p, p0, q32.p, base, pt, st);
+        launch_reduce(RED_BETA, 1, pt, nb, base, nullptr, st);
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), beta_block, 0, st, base, ms, gl, ns, (int)CG_RUNNING);
+        hipLaunchKernelGGL(k_ms_update<F32>, dim3((vh + 255) / 256), dim3(256), 0, st, X, P, Rv, base, ms, ns,
+                           (int)CG_RUNNING);
+        hipLaunchKernelGGL(k_ms_clear_pending, dim3(gb), dim3(tb), 0, st, base, ms, ns, (int)CG_RUNNING);
+        launch_update_p(F32, vh, 1, r32.p, p0, base, CG_RUNNING, st);
+        return (int)(hipGetLastError() == hipSuccess ? HISQ_OK : HISQ_ERR_HIP);
+    };
+    // FP64 reliable update of the base system (runs when the base flag is CG_ATTENTION)
+    auto reliable = [&]() -> int {
+        int r2;
+        launch_accum_zero(F32, vh, 1, xhi, x32.p, base, CG_ATTENTION, s);
+        if ((r2 = gauge_dslash(g, 1, F64, F64, F64, 1, xhi, t64.p, nullptr, nullptr, nullptr, nullptr, s))) return r2;
+        if ((r2 = gauge_dslash(g, 0, F64, F64, F64, 1, t64.p, ax64.p, xhi, (const double *)diag.p, pt, nullptr, s)))
+            return r2;
+        launch_residual(vh, 1, b, ax64.p, r64.p, base, CG_ATTENTION, pt, s);
+        launch_reduce(RED_TRUE, 1, pt, nb, base, nullptr, s);
+        launch_convert(F64, F32, vh, 1, r64.p, r32.p, base, CG_RESUME, s);
+        // the shifts' beta and direction updates of this iteration, from the new residual
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), beta_block, 0, s, base, ms, gl, ns, (int)CG_RESUME);
+        hipLaunchKernelGGL(k_ms_update<F32>, dim3((vh + 255) / 256), dim3(256), 0, s, X, P, Rv, base, ms, ns,
+                           (int)CG_RESUME);
+        hipLaunchKernelGGL(k_ms_clear_pending, dim3(gb), dim3(tb), 0, s, base, ms, ns, (int)CG_RESUME);
+        launch_update_p(F32, vh, 1, r32.p, p0, base, CG_RESUME, s);
+        launch_resume_flags(1, base, s);
+        return (int)(hipGetLastError() == hipSuccess ? HISQ_OK : HISQ_ERR_HIP);
+    };
+
+    const int chunk = std::max(1, prm.graph_chunk > 0 ? prm.graph_chunk : 8);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const bool use_graph = prm.graph_chunk > 0;
+    rc = HISQ_OK;
+    if (use_graph) {
+        hipStream_t cs = g->capture_stream;
+        HISQ_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < chunk && rc == HISQ_OK; ++i) rc = iteration(cs);
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (rc == HISQ_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (rc || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (!rc) set_error(std::string("multishift graph: ") + hipGetErrorString(e));
+            return rc ? rc : HISQ_ERR_HIP;
+        }
+    }
+    const long max_chunks = 2L * prm.max_iter + 16;  // chunk replays and reliable updates
+    for (long c = 0; c < max_chunks && rc == HISQ_OK; ++c) {
+        HISQ_HIP_CHECK(hipMemcpyAsync(&hb, base, sizeof(hb), hipMemcpyDeviceToHost, s));
+        HISQ_HIP_CHECK(hipStreamSynchronize(s));
+        if (hb.flag == CG_ATTENTION) {
+            rc = reliable();
+            continue;
+        }
+        if (hb.flag != CG_RUNNING) break;
+        if (use_graph) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) rc = HISQ_ERR_HIP;
+        } else {
+            for (int i = 0; i < chunk && rc == HISQ_OK; ++i) rc = iteration(s);
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    HISQ_HIP_CHECK(hipMemcpyAsync(&hb, base, sizeof(hb), hipMemcpyDeviceToHost, s));
+    HISQ_HIP_CHECK(hipStreamSynchronize(s));
+    const int iters_total = hb.iter, base_ru = hb.reliable;
+    // a breakdown or a stop at the cap leaves the base's sloppy part unfolded
+    if (hb.flag != CG_DONE) launch_accum_zero(F32, vh, 1, xhi, x32.p, base, hb.flag, s);
+    hipLaunchKernelGGL(k_ms_flush<F32>, dim3((vh + 255) / 256), dim3(256), 0, s, X, P, ms, ns);
+    HISQ_HIP_CHECK(hipMemcpyAsync(hm.data(), ms, sizeof(MsState) * ns, hipMemcpyDeviceToHost, s));
+    if (ns > 1)
+        launch_convert(F32, F64, vh, ns - 1, (char *)x32.p + s32, (char *)x64.p + s64, nullptr, -1, s);
+
+    // every shift finished on its FP64 true residual by the batched mixed CG
+    static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
+    if (trace) {
+        HISQ_HIP_CHECK(hipStreamSynchronize(s));
+        std::fprintf(stderr, "[multishift] mixed: %d shifts, %d base iterations, %d reliable updates, %.3f s\n", ns,
+                     iters_total, base_ru, std::chrono::duration<double>(clk::now() - t0).count());
+    }
+    hipLaunchKernelGGL(k_replicate<F64>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh),
+                       spinor_view<F64>(bstack.p, vh));
+    HISQ_HIP_CHECK(hipGetLastError());
+    std::vector<double> sig(ns);
+    for (int k = 0; k < ns; ++k) sig[k] = shifts[order[k]];
+    hisq_solver_params rp = prm;
+    rp.warm_start = 1;
+    std::vector<hisq_solver_stats> rs(ns);
+    int worst = cg_solve(g, mass, ns, (const double *)bstack.p, (double *)x64.p, sig.data(), rp, rs.data(), s);
+    if (worst < 0) return worst;
+    for (int k = 0; k < ns; ++k)
+        HISQ_HIP_CHECK(hipMemcpyAsync((char *)x + s64 * order[k], (char *)x64.p + s64 * k, s64,
+                                      hipMemcpyDeviceToDevice, s));
+    HISQ_HIP_CHECK(hipStreamSynchronize(s));
+    const double total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (trace) {
+        int most = 0;
+        for (int k = 0; k < ns; ++k) most = std::max(most, rs[k].iterations);
+        std::fprintf(stderr, "[multishift] refinement: at most %d iterations, total %.3f s\n", most, total_ms / 1e3);
+    }
+    if (stats) {
+        const double per_iter = (double)(dslash_algorithmic_bytes(F32, F32, F32, vh, 1, false, g->comp_mode) +
+                                         dslash_algorithmic_bytes(F32, F32, F32, vh, 1, true, g->comp_mode));
+        const double per_ru = (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->comp_mode) +
+                                       dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->comp_mode));
+        for (int k = 0; k < ns; ++k) {
+            hisq_solver_stats o = rs[k];
+            o.iterations = (k == 0 ? iters_total : hm[k].iters) + rs[k].iterations;
+            o.wall_ms = total_ms;
+            o.reliable_updates = (k == 0 ? base_ru : 0) + rs[k].reliable_updates;
+            o.dslash_bytes = ((double)iters_total * per_iter + (double)base_ru * per_ru) / ns + rs[k].dslash_bytes;
+            stats[order[k]] = o;
+        }
+    }
+    return worst;
+}
 
 int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts, const double *b, double *x,
                      const hisq_solver_params &prm, hisq_solver_stats *stats, hipStream_t s) {
@@ -156,6 +375,8 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     std::vector<int> order(ns);
     for (int k = 0; k < ns; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return shifts[a] < shifts[c]; });
+    if (prm.sloppy_prec != HISQ_PREC_FP64)
+        return multishift_solve_mixed(g, mass, ns, order.data(), shifts, b, x, prm, stats, s);
     const double sig0 = shifts[order[0]];
 
     const size_t s64 = spinor_bytes(F64, vh);
@@ -188,7 +409,7 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
 
     CgState hb;
     std::memset(&hb, 0, sizeof(hb));
-    hb.stop2 = prm.tol * prm.tol * b2;
+    hb.stop2 = kResidualMargin * kResidualMargin * prm.tol * prm.tol * b2;
     hb.true2 = hb.stop2;
     hb.max_iter = prm.max_iter;
     hb.flag = CG_ATTENTION;
@@ -210,7 +431,7 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     launch_reduce(RED_INIT, 1, (double *)w.part.p, nb, base, nullptr, s);
     launch_zero(F64, vh, ns, xs.p, s);
     const dim3 rep_grid((vh + 255) / 256, ns);
-    hipLaunchKernelGGL(k_replicate, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), P);
+    hipLaunchKernelGGL(k_replicate<F64>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), P);
     HISQ_HIP_CHECK(hipGetLastError());
 
     const int chunk = std::max(1, prm.graph_chunk > 0 ? prm.graph_chunk : 8);
@@ -228,9 +449,10 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
         launch_update_xr(F64, vh, 1, xs.p, w.r.p, p0, w.q.p, base, (double *)w.part.p, st);
         launch_reduce(RED_BETA, 1, (double *)w.part.p, nb, base, nullptr, st);
         hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(std::max(64, ((ns + 63) / 64) * 64)), 0, st, base, ms,
-                           gl, ns);
-        hipLaunchKernelGGL(k_ms_update, dim3((vh + 255) / 256), dim3(256), 0, st, X, P, Rv, base, ms, ns);
-        hipLaunchKernelGGL(k_ms_clear_pending, dim3(gb), dim3(tb), 0, st, base, ms, ns);
+                           gl, ns, (int)CG_RUNNING);
+        hipLaunchKernelGGL(k_ms_update<F64>, dim3((vh + 255) / 256), dim3(256), 0, st, X, P, Rv, base, ms, ns,
+                           (int)CG_RUNNING);
+        hipLaunchKernelGGL(k_ms_clear_pending, dim3(gb), dim3(tb), 0, st, base, ms, ns, (int)CG_RUNNING);
         launch_update_p(F64, vh, 1, w.r.p, p0, base, CG_RUNNING, st);
         return (int)(hipGetLastError() == hipSuccess ? HISQ_OK : HISQ_ERR_HIP);
     };
@@ -265,13 +487,13 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     iters_total = hb.iter;
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    hipLaunchKernelGGL(k_ms_flush, dim3((vh + 255) / 256), dim3(256), 0, s, X, P, ms, ns);
+    hipLaunchKernelGGL(k_ms_flush<F64>, dim3((vh + 255) / 256), dim3(256), 0, s, X, P, ms, ns);
     HISQ_HIP_CHECK(hipMemcpyAsync(hm.data(), ms, sizeof(MsState) * ns, hipMemcpyDeviceToHost, s));
 
     // FP64 verification and refinement of every shift: batched CG warm-started
     // from the multi-shift solutions (converged shifts leave at once).
     Spinor<F64> Bs = spinor_view<F64>(w.bstack.p, vh);
-    hipLaunchKernelGGL(k_replicate, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), Bs);
+    hipLaunchKernelGGL(k_replicate<F64>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), Bs);
     std::vector<double> sig(ns);
     for (int k = 0; k < ns; ++k) sig[k] = shifts[order[k]];
     hisq_solver_params rp = prm;
@@ -293,8 +515,8 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
             o.iterations = (k == 0 ? iters_total : hm[k].iters) + rs[k].iterations;
             o.wall_ms = total_ms;
             o.reliable_updates = rs[k].reliable_updates;
-            o.dslash_bytes = (double)iters_total * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
-                                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed)) /
+            o.dslash_bytes = (double)iters_total * (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->comp_mode) +
+                                                            dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->comp_mode)) /
                                  ns +
                              rs[k].dslash_bytes;
             stats[order[k]] = o;

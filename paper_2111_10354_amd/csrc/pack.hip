@@ -40,48 +40,62 @@ __device__ void store_slot(void *dst, int k, int h, const cx<double> w[9]) {
     }
 }
 
-// Compressed layout: fat slots whole, long slots as rows 0 and 1 plus the
-// determinant sign bit (see CompGeom).
+// Compressed layouts: fat slots whole, long slots as rows 0 and 1 plus the
+// determinant sign bit (COMP_SIGN) or the complex factor kappa = det / s^4,
+// s^2 = tr(M M^+) / 3 (COMP_KAPPA), see CompGeom.
+__device__ inline cx<double> det3(const cx<double> w[9]) {
+    const cx<double> a = cmul(w[4], w[8]), b = cmul(w[5], w[7]);
+    const cx<double> c2 = cmul(w[3], w[8]), d2 = cmul(w[5], w[6]);
+    const cx<double> e2 = cmul(w[3], w[7]), f2 = cmul(w[4], w[6]);
+    const cx<double> t0 = cmul(w[0], {a.re - b.re, a.im - b.im}), t1 = cmul(w[1], {c2.re - d2.re, c2.im - d2.im}),
+                     t2 = cmul(w[2], {e2.re - f2.re, e2.im - f2.im});
+    return {t0.re - t1.re + t2.re, t0.im - t1.im + t2.im};
+}
+
 template <int F>
-__device__ void store_slot_comp(void *dst, int vh, int k, int h, const cx<double> w[9]) {
-    constexpr int MC = CompGeom<F>::MC, NC = CompGeom<F>::NC, UF = CompGeom<F>::UF, UC = UF + CompGeom<F>::UL;
+__device__ void store_entry(char *q, cx<double> v) {
+    if constexpr (F == F64) {
+        *(d2v *)q = d2v{v.re, v.im};
+    } else if constexpr (F == F32) {
+        *(f2v *)q = f2v{(float)v.re, (float)v.im};
+    } else {
+        *(h2v *)q = __builtin_convertvector((f2v{(float)v.re, (float)v.im}), h2v);
+    }
+}
+
+template <int F>
+__device__ void store_slot_comp(void *dst, int vh, int k, int h, const cx<double> w[9], int mode) {
+    constexpr int MC = CompGeom<F>::MC, NC = CompGeom<F>::NC, UF = CompGeom<F>::UF, UL = CompGeom<F>::UL;
     constexpr int CSIZE = F == F64 ? 16 : F == F32 ? 8 : 4;  // bytes per complex entry
+    const int UC = comp_chunk_units<F>(mode);
     const int mu = k >> 2, j = k & 3, c = mu / MC, sm = mu % MC;
     char *rec = (char *)dst + ((size_t)((h >> 6) * NC + c) * UC) * 1024 + (size_t)(h & 63) * 16;
     const int n = j < 2 ? 9 : 6;
     const int first = j < 2 ? (2 * sm + j) * 9 * CSIZE : UF * 16 + (2 * sm + j - 2) * 6 * CSIZE;
     for (int e = 0; e < n; ++e) {
         const int off = first + e * CSIZE;
-        char *q = rec + (size_t)(off >> 4) * 1024 + (off & 15);
-        if constexpr (F == F64) {
-            *(d2v *)q = d2v{w[e].re, w[e].im};
-        } else if constexpr (F == F32) {
-            *(f2v *)q = f2v{(float)w[e].re, (float)w[e].im};
-        } else {
-            *(h2v *)q = __builtin_convertvector((f2v{(float)w[e].re, (float)w[e].im}), h2v);
-        }
+        store_entry<F>(rec + (size_t)(off >> 4) * 1024 + (off & 15), w[e]);
     }
-    if (j >= 2) {
-        // determinant of the slot matrix (+-1 for compressible long links)
-        const cx<double> a = cmul(w[4], w[8]), b = cmul(w[5], w[7]);
-        const cx<double> c2 = cmul(w[3], w[8]), d2 = cmul(w[5], w[6]);
-        const cx<double> e2 = cmul(w[3], w[7]), f2 = cmul(w[4], w[6]);
-        const cx<double> m0 = {a.re - b.re, a.im - b.im}, m1 = {c2.re - d2.re, c2.im - d2.im},
-                         m2 = {e2.re - f2.re, e2.im - f2.im};
-        const cx<double> t0 = cmul(w[0], m0), t1 = cmul(w[1], m1), t2 = cmul(w[2], m2);
-        const double det_re = t0.re - t1.re + t2.re;
-        if (det_re < 0.0) {
-            const size_t tiles = (size_t)(vh + LINK_TILE - 1) / LINK_TILE;
-            unsigned *sg = (unsigned *)((char *)dst + tiles * comp_units_per_site(F) * 1024);
-            atomicOr(sg + h, 1u << (2 * mu + j - 2));
-        }
+    if (j < 2) return;
+    const cx<double> det = det3(w);
+    if (mode == COMP_KAPPA) {
+        double s2 = 0.0;
+        for (int e = 0; e < 9; ++e) s2 += w[e].re * w[e].re + w[e].im * w[e].im;
+        s2 /= 3.0;
+        const double inv = 1.0 / (s2 * s2);
+        const int off = (UF + UL) * 16 + (2 * sm + j - 2) * CSIZE;
+        store_entry<F>(rec + (size_t)(off >> 4) * 1024 + (off & 15), cx<double>{det.re * inv, det.im * inv});
+    } else if (det.re < 0.0) {  // determinant +-1
+        const size_t tiles = (size_t)(vh + LINK_TILE - 1) / LINK_TILE;
+        unsigned *sg = (unsigned *)((char *)dst + tiles * comp_units_per_site(F, COMP_SIGN) * 1024);
+        atomicOr(sg + h, 1u << (2 * mu + j - 2));
     }
 }
 
 template <int F>
 __global__ __launch_bounds__(256) void k_pack_links(Geom g, const double *__restrict__ fat,
                                                     const double *__restrict__ lng, void *dst,
-                                                    int parity, unsigned int *maxabs_bits, int compressed) {
+                                                    int parity, unsigned int *maxabs_bits, int comp_mode) {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     if (h >= g.vh) return;
@@ -103,39 +117,47 @@ __global__ __launch_bounds__(256) void k_pack_links(Geom g, const double *__rest
             }
             m = fmaxf(m, fmaxf(fabsf((float)w[3 * a + b].re), fabsf((float)w[3 * a + b].im)));
         }
-    if (compressed) store_slot_comp<F>(dst, g.vh, k, h, w);
+    if (comp_mode != COMP_NONE) store_slot_comp<F>(dst, g.vh, k, h, w, comp_mode);
     else store_slot<F>(dst, k, h, w);
     if (maxabs_bits) atomicMax(maxabs_bits, __float_as_uint(m));  // m >= 0: bit order = value order
 }
 
-// Deviation of each long link L from a unitary matrix with determinant +-1.
+// Deviation of each long link L from a unitary matrix with determinant +-1
+// (bits[0]) and from a positive multiple of a unitary matrix (bits[1]).
 __global__ __launch_bounds__(256) void k_long_defect(int64_t V, const double *__restrict__ lng, unsigned *bits) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (site, mu)
     if (i >= 4 * V) return;
     const double *U = lng + (size_t)i * 18;
     cx<double> m[9];
     for (int e = 0; e < 9; ++e) m[e] = {U[2 * e], U[2 * e + 1]};
-    double dev = 0.0;
+    double ll[9][2];
+    double s2 = 0.0;
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {  // (L L^+)_ab - delta_ab
-            double re = a == b ? -1.0 : 0.0, im = 0.0;
+        for (int b = 0; b < 3; ++b) {  // (L L^+)_ab
+            double re = 0.0, im = 0.0;
             for (int c = 0; c < 3; ++c) {
                 const cx<double> x = m[3 * a + c], y = m[3 * b + c];
                 re += x.re * y.re + x.im * y.im;
                 im += x.im * y.re - x.re * y.im;
             }
-            dev = fmax(dev, fmax(fabs(re), fabs(im)));
+            ll[3 * a + b][0] = re;
+            ll[3 * a + b][1] = im;
+            if (a == b) s2 += re;
         }
-    const cx<double> a = cmul(m[4], m[8]), b = cmul(m[5], m[7]);
-    const cx<double> c2 = cmul(m[3], m[8]), d2 = cmul(m[5], m[6]);
-    const cx<double> e2 = cmul(m[3], m[7]), f2 = cmul(m[4], m[6]);
-    const cx<double> t0 = cmul(m[0], {a.re - b.re, a.im - b.im}), t1 = cmul(m[1], {c2.re - d2.re, c2.im - d2.im}),
-                     t2 = cmul(m[2], {e2.re - f2.re, e2.im - f2.im});
-    const double dr = t0.re - t1.re + t2.re, di = t0.im - t1.im + t2.im;
-    dev = fmax(dev, fmax(fabs(fabs(dr) - 1.0), fabs(di)));
-    if (!(dev == dev)) dev = 1e30;  // NaN: not compressible
-    const float f = (float)fmin(dev, 1e30);
-    atomicMax(bits, __float_as_uint(f));
+    s2 /= 3.0;
+    double dev1 = 0.0, dev2 = 0.0;
+    for (int e = 0; e < 9; ++e) {
+        const double d = (e % 4 == 0) ? 1.0 : 0.0;
+        dev1 = fmax(dev1, fmax(fabs(ll[e][0] - d), fabs(ll[e][1])));
+        dev2 = fmax(dev2, fmax(fabs(ll[e][0] - d * s2), fabs(ll[e][1])));
+    }
+    dev2 = s2 > 0.0 ? dev2 / s2 : 1e30;
+    const cx<double> det = det3(m);
+    dev1 = fmax(dev1, fmax(fabs(fabs(det.re) - 1.0), fabs(det.im)));
+    if (!(dev1 == dev1)) dev1 = 1e30;  // NaN: not compressible
+    if (!(dev2 == dev2)) dev2 = 1e30;
+    atomicMax(bits, __float_as_uint((float)fmin(dev1, 1e30)));
+    atomicMax(bits + 1, __float_as_uint((float)fmin(dev2, 1e30)));
 }
 
 void launch_long_link_defect(const Geom &g, const double *lng, unsigned *defect_bits, hipStream_t s) {
@@ -144,26 +166,25 @@ void launch_long_link_defect(const Geom &g, const double *lng, unsigned *defect_
 }
 
 int launch_pack_links(const Geom &g, int fmt, const double *fat, const double *lng, void *dst_even,
-                      void *dst_odd, float *maxabs_dev, bool compressed, hipStream_t s) {
+                      void *dst_odd, float *maxabs_dev, int comp_mode, hipStream_t s) {
     dim3 grid((g.vh + 255) / 256, 16);
-    const int comp = compressed ? 1 : 0;
     for (int par = 0; par < 2; ++par) {
         void *dst = par ? dst_odd : dst_even;
-        if (compressed) {  // determinant sign words start at zero
+        if (comp_mode == COMP_SIGN) {  // determinant sign words start at zero
             const size_t tiles = (size_t)(g.vh + LINK_TILE - 1) / LINK_TILE;
-            HISQ_HIP_CHECK(hipMemsetAsync((char *)dst + tiles * comp_units_per_site(fmt) * 1024, 0,
+            HISQ_HIP_CHECK(hipMemsetAsync((char *)dst + tiles * comp_units_per_site(fmt, COMP_SIGN) * 1024, 0,
                                           tiles * LINK_TILE * 4, s));
         }
         unsigned int *mb = (unsigned int *)maxabs_dev;
         switch (fmt) {
             case F64:
-                hipLaunchKernelGGL(k_pack_links<F64>, grid, dim3(256), 0, s, g, fat, lng, dst, par, mb, comp);
+                hipLaunchKernelGGL(k_pack_links<F64>, grid, dim3(256), 0, s, g, fat, lng, dst, par, mb, comp_mode);
                 break;
             case F32:
-                hipLaunchKernelGGL(k_pack_links<F32>, grid, dim3(256), 0, s, g, fat, lng, dst, par, mb, comp);
+                hipLaunchKernelGGL(k_pack_links<F32>, grid, dim3(256), 0, s, g, fat, lng, dst, par, mb, comp_mode);
                 break;
             case H16:
-                hipLaunchKernelGGL(k_pack_links<H16>, grid, dim3(256), 0, s, g, fat, lng, dst, par, mb, comp);
+                hipLaunchKernelGGL(k_pack_links<H16>, grid, dim3(256), 0, s, g, fat, lng, dst, par, mb, comp_mode);
                 break;
             default: return HISQ_ERR_INVALID;
         }

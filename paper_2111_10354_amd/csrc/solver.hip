@@ -5,9 +5,9 @@
 //   t   = D_oe p                      (Dslash, sloppy precision)
 //   q   = diag_i p - D_eo t           (Dslash epilogue) and partial Re<p, q>
 //   alpha = rho / Re<p, q>            (single-block reduction, device scalars)
-//   x  += alpha p ; r -= alpha q      and partial |r|^2
+//   r  -= alpha q                     and partial |r|^2
 //   rho' = |r|^2 ; flag if |r| <= tol|b|, a reliable update is due or the cap
-//   p   = r + (rho'/rho) p
+//   x  += alpha p ; p = r + (rho'/rho) p   (one pass; p only if still running)
 // A chunk of such iterations is captured once into a hipGraph and replayed;
 // flagged RHS turn every later kernel of the chunk into a no-op.  Between
 // chunks the host looks at the per-RHS flags and, for flagged RHS, performs
@@ -47,8 +47,11 @@ int DevBuf::alloc(size_t n) {
 
 static size_t real_bytes(int f) { return f == F64 ? 8 : f == F32 ? 4 : 2; }
 
-size_t dslash_algorithmic_bytes(int fl, int fi, int fo, int64_t vh, int nrhs, bool epi, bool comp) {
-    const size_t links = (comp && fl != F64) ? (8 * 18 + 8 * 12) * real_bytes(fl) + 4 : 16 * 18 * real_bytes(fl);
+size_t dslash_algorithmic_bytes(int fl, int fi, int fo, int64_t vh, int nrhs, bool epi, int comp) {
+    if (fl == F64) comp = COMP_NONE;
+    const size_t links = comp == COMP_SIGN    ? (8 * 18 + 8 * 12) * real_bytes(fl) + 4
+                         : comp == COMP_KAPPA ? (8 * 18 + 8 * 12 + 8 * 2) * real_bytes(fl)
+                                              : 16 * 18 * real_bytes(fl);
     const size_t per_rhs = spinor_bytes(fi, 1) + spinor_bytes(fo, 1) + (epi ? spinor_bytes(fi, 1) : 0);
     return (size_t)vh * (links + (size_t)nrhs * per_rhs);
 }
@@ -90,7 +93,7 @@ int gauge_dslash(hisq_gauge_s *g, int out_parity, int fl, int fi, int fo, int nr
     a.tile = sh.tile;
     a.block = sh.block;
     a.order = sh.order;
-    a.compressed = links_compressed(g, fl) ? 1 : 0;
+    a.compressed = links_compressed(g, fl);
     return launch_dslash(g->geom, a, s);
 }
 
@@ -119,7 +122,8 @@ static int ws_alloc(CgWorkspace &w, const Geom &g, int n, int fmt) {
 }
 
 int nb_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int n, bool epi) {
-    return dslash_grid_blocks(g->geom, pick_shape(g, fl, fi, fo, n, epi).block);
+    const DslashShape sh = pick_shape(g, fl, fi, fo, n, epi);
+    return dslash_grid_blocks(g->geom, sh.block, sh.order);
 }
 
 // One CG iteration for every running RHS of the workspace.
@@ -132,9 +136,11 @@ static int cg_iteration(hisq_gauge_s *g, CgWorkspace &w, hipStream_t s) {
                            (double *)w.part.p, w.st(), s)))
         return rc;
     launch_reduce(RED_ALPHA, n, (double *)w.part.p, nb_dslash(g, LF, S, fq, n, true), w.st(), nullptr, s);
-    launch_update_xr(S, vh, n, w.X(), w.R(), w.P(), w.Q(), w.st(), (double *)w.part.p, s);
+    launch_update_r(S, vh, n, w.R(), w.Q(), w.st(), (double *)w.part.p, s);
     launch_reduce(RED_BETA, n, (double *)w.part.p, blas_blocks(vh), w.st(), nullptr, s);
-    launch_update_p(S, vh, n, w.R(), w.P(), w.st(), CG_RUNNING, s);
+    // x += alpha p with the direction of this iteration, in the pass that
+    // replaces p (each of x, p, r read once)
+    launch_update_xp(S, vh, n, w.X(), w.R(), w.P(), w.st(), s);
     return HISQ_OK;
 }
 
@@ -245,9 +251,10 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     for (int i = 0; i < n; ++i) {
         CgState &c = hs[i];
         std::memset(&c, 0, sizeof(c));
-        c.stop2 = prm.tol * prm.tol * b2[i];
+        c.stop2 = kResidualMargin * kResidualMargin * prm.tol * prm.tol * b2[i];
         c.true2 = c.stop2;
         c.ru_period = (S == F64) ? 0 : std::max(1, prm.ru_period);
+        c.ru_delta2 = (S == F64) ? 0.0 : prm.ru_delta * prm.ru_delta;
         c.max_iter = prm.max_iter;
         c.flag = CG_ATTENTION;
     }
@@ -277,7 +284,9 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     // HISQ_SOLVER_TRACE=1 prints the progress every 2000 iterations to stderr
     static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
     int next_report = 2000;
-    const long max_chunks = (long)prm.max_iter / chunk + 2 * (prm.max_iter / std::max(1, prm.ru_period)) + 16;
+    // every pass either replays a chunk (at least one iteration of each running
+    // RHS) or performs the reliable updates that the last chunk flagged
+    const long max_chunks = 2L * prm.max_iter + 16;
     for (long c = 0; c < max_chunks; ++c) {
         HISQ_HIP_CHECK(hipMemcpyAsync(hs.data(), w.state.p, sizeof(CgState) * n, hipMemcpyDeviceToHost, s));
         HISQ_HIP_CHECK(hipStreamSynchronize(s));
@@ -337,11 +346,11 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
             o.true_residual = tr;
             o.wall_ms = ms;
             o.dslash_bytes = (double)c.iter *
-                                 (double)(dslash_algorithmic_bytes(LF, S, S, vh, 1, false, g->compressed) +
-                                          dslash_algorithmic_bytes(LF, S, S == H16 ? F32 : S, vh, 1, true, g->compressed)) +
+                                 (double)(dslash_algorithmic_bytes(LF, S, S, vh, 1, false, g->comp_mode) +
+                                          dslash_algorithmic_bytes(LF, S, S == H16 ? F32 : S, vh, 1, true, g->comp_mode)) +
                              (double)(c.reliable + 1) *
-                                 (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->compressed) +
-                                          dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->compressed));
+                                 (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->comp_mode) +
+                                          dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->comp_mode));
         }
     }
     return worst;

@@ -34,7 +34,7 @@ class HisqError(RuntimeError):
 class SolverParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("sloppy_prec", C.c_int),
                 ("ru_period", C.c_int), ("graph_chunk", C.c_int), ("warm_start", C.c_int),
-                ("fallback", C.c_int), ("precond", C.c_void_p)]
+                ("fallback", C.c_int), ("precond", C.c_void_p), ("ru_delta", C.c_double)]
 
 
 class SolverStats(C.Structure):
@@ -84,6 +84,7 @@ def _load():
         "hisq_zolotarev_inv_sqrt": (C.c_int, [C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
         "hisq_rational_remez": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
         "hisq_spectral_bounds": (C.c_int, [vp, C.c_double, C.c_int, dp, dp, vp]),
+        "hisq_smear_links": (C.c_int, [ip, vp, vp, vp, C.c_uint, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -102,7 +103,7 @@ EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_c
            "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
            "hisq_nn_train_step", "hisq_gauge_links_compressed", "hisq_rational_apply",
            "hisq_zolotarev_inv_sqrt", "hisq_rational_remez", "hisq_spectral_bounds",
-           "hisq_dslash_multi_rhs_noalloc")
+           "hisq_dslash_multi_rhs_noalloc", "hisq_smear_links")
 
 LINKS_FULL = 1 << 8  # hisq_gauge_create: store every link whole
 
@@ -186,7 +187,12 @@ class Gauge:
     @property
     def compressed(self) -> bool:
         """True if the FP32 / FP16 long links are stored as two rows (see hisq_gauge_create)."""
-        return bool(_check(LIB.hisq_gauge_links_compressed(self.handle), allow_soft=True))
+        return self.comp_mode != 0
+
+    @property
+    def comp_mode(self) -> int:
+        """0 long links whole, 1 two rows + determinant sign, 2 two rows + complex factor."""
+        return int(_check(LIB.hisq_gauge_links_compressed(self.handle), allow_soft=True))
 
     def device_bytes(self) -> int:
         n = C.c_size_t()
@@ -339,6 +345,22 @@ def dslash_shape(g: Gauge, prec, nrhs: int, epilogue: int = 0):
     out = (C.c_int * 3)()
     _check(LIB.hisq_dslash_shape(g.handle, _prec(prec), int(nrhs), int(epilogue), out))
     return tuple(out)
+
+
+SMEAR_ANTIPERIODIC_T = 1
+
+
+def smear_links(dims, thin, fat, lng, antiperiodic_t: bool = False, stream=None):
+    """HISQ fat and Naik links (phases folded) from thin links: complex128 [V,4,3,3]
+    device tensors, fat and lng written."""
+    V = 1
+    for d in dims:
+        V *= int(d)
+    for t, what in ((thin, "thin"), (fat, "fat"), (lng, "lng")):
+        _need(t, V * 4 * 9 * 16, what)
+    d = (C.c_int * 4)(*[int(v) for v in dims])
+    _check(LIB.hisq_smear_links(d, _ptr(thin), _ptr(fat), _ptr(lng),
+                                SMEAR_ANTIPERIODIC_T if antiperiodic_t else 0, _stream(stream)))
 
 
 def gauge_set_thin(g: Gauge, thin: torch.Tensor, stream=None):

@@ -291,14 +291,15 @@ def thin_links(dims, cfg_id: int, eps: float, workers: int | None = None, out=No
 
 
 def hisq_links(dims, cfg_id: int, eps: float, antiperiodic_t: bool = False,
-               want_thin: bool = False, workers: int | None = None, fold: bool = True, out=None):
+               want_thin: bool = False, workers: int | None = None, fold: bool = True, out=None, thin=None):
     """Folded fat and Naik links of the benchmark recipe.
 
     Returns ``(fat, long)`` or ``(fat, long, thin)`` where ``thin`` is the thin
     field with the same phases and one-hop boundary signs folded in.  With
     ``fold=False`` no phase or boundary sign is applied (used to check the
     folding against an operator that applies them itself).  ``out``: arrays
-    (shared with forked workers) to write the result into.
+    (shared with forked workers) to write the result into.  ``thin``: the
+    unfolded thin links of these arguments (``thin_links``), if already made.
 
     Large lattices are built by a pool of forked worker processes.  Once this
     process has initialised the GPU, the pool runs in a fresh child interpreter
@@ -307,10 +308,10 @@ def hisq_links(dims, cfg_id: int, eps: float, antiperiodic_t: bool = False,
     _check_dims(dims)
     V = volume(dims)
     workers = _default_workers(V) if workers is None else workers
-    if out is None and workers > 1 and _gpu_initialised():
+    if out is None and thin is None and workers > 1 and _gpu_initialised():
         return _in_child("hisq", 3 if want_thin else 2, V, dims=list(dims), cfg_id=cfg_id, eps=eps,
                          apbc=bool(antiperiodic_t), fold=bool(fold))
-    U = thin_links(dims, cfg_id, eps, workers)
+    U = thin if thin is not None else thin_links(dims, cfg_id, eps, workers)
     alloc = (lambda: _shared_array((V, 4, 3, 3))) if workers > 1 else \
         (lambda: np.empty((V, 4, 3, 3), np.complex128))
     if out is not None:
@@ -328,6 +329,15 @@ def hisq_links(dims, cfg_id: int, eps: float, antiperiodic_t: bool = False,
         _SHARED.clear()
     del U
     return (F, L, T) if want_thin else (F, L)
+
+
+def hisq_links_and_thin(dims, cfg_id: int, eps: float):
+    """(fat, long, unfolded thin) of the benchmark recipe, the thin links made once."""
+    V = volume(dims)
+    workers = _default_workers(V)
+    U = thin_links(dims, cfg_id, eps, workers)
+    F, L = hisq_links(dims, cfg_id, eps, workers=workers, thin=U)  # forked workers only read U
+    return F, L, U
 
 
 def free_links(dims, c1: float, c3: float, antiperiodic_t: bool = False):

@@ -7,8 +7,9 @@
 //  * the decoded coordinates give back the site and its parity;
 //  * each of the 16 hops lands on the site a coordinate-based reference gives,
 //    of the other parity, inside [0, Vh);
-//  * every 16-byte link unit a thread reads, whole or compressed layout, lies
-//    inside the packed buffer, and the sign word inside the sign plane.
+//  * every 16-byte link unit a thread reads, whole or compressed layout (sign
+//    or kappa mode), lies inside the packed buffer, and the sign word inside
+//    the sign plane.
 // Prints one line per lattice and exits non-zero on the first violation.
 #include <cstdio>
 #include <cstdlib>
@@ -31,8 +32,8 @@ static int fails = 0;
 static long lex_of(const int L[4], const int c[4]) { return c[0] + (long)L[0] * (c[1] + (long)L[1] * (c[2] + (long)L[2] * c[3])); }
 
 // units of 16 bytes in one parity's packed links
-static long whole_units(int f, long vh) { return (long)link_parity_bytes(f, vh, false) / 16; }
-static long comp_units_total(int f, long vh) { return (long)link_parity_bytes(f, vh, true) / 16; }
+static long whole_units(int f, long vh) { return (long)link_parity_bytes(f, vh, COMP_NONE) / 16; }
+static long comp_units_total(int f, long vh, int mode) { return (long)link_parity_bytes(f, vh, mode) / 16; }
 
 static void check_lattice(const int dims[4], bool quick) {
     const Geom g = make_geom(dims);
@@ -43,15 +44,20 @@ static void check_lattice(const int dims[4], bool quick) {
     long launches = 0;
     for (int parity = 0; parity < 2; ++parity) {
         for (int block : {64, 128, 256}) {
-            const int nb = (int)((vh + block - 1) / block);
-            for (int order : orders) {
+            for (int base : orders)
+            for (int rsl = 0; rsl <= 2; ++rsl) {
+                // RHS split over 1, 2, 4 waves: the kernel maps its block of
+                // `block` threads onto block / RS sites with the tile order bits
+                const int order = base | rsl << 24, sb = block >> rsl;
                 if (!order_supported(g, order, block)) continue;
-                if (quick && order > 1 && order != orders[2 + 7]) continue;
+                if (quick && (rsl || (base > 1 && base != orders[2 + 7]))) continue;
                 ++launches;
+                const int nbs = dslash_grid_blocks(g, block, order);
+                CHECK(nbs == (int)((vh + sb - 1) / sb), "grid of %d blocks for block %d split %d", nbs, block, 1 << rsl);
                 std::vector<unsigned char> seen(vh, 0);
-                for (int blk = 0; blk < nb; ++blk)
-                    for (int tid = 0; tid < block; ++tid) {
-                        const int h = site_of_thread(g, blk, nb, block, tid, order);
+                for (int blk = 0; blk < nbs; ++blk)
+                    for (int tid = 0; tid < sb; ++tid) {
+                        const int h = site_of_thread(g, blk, nbs, sb, tid, base);
                         if (h >= vh) continue;  // grid tail, skipped by the kernel's guard
                         CHECK(h >= 0, "negative site %d (order %d block %d)", h, order, block);
                         CHECK(!seen[h], "site %d twice (order %d block %d)", h, order, block);
@@ -84,22 +90,45 @@ static void check_lattice(const int dims[4], bool quick) {
                     CHECK(u >= 0 && u + 8 * 64 < whole_units(f, vh), "whole link unit %ld of site %ld fmt %d", u, h, f);
                 }
             }
-            // compressed layout (FP32 and FP16) and its sign word
+            // compressed layouts (FP32 and FP16): sign mode with its sign word,
+            // kappa mode with its kappa unit (the last unit of every chunk)
             {
-                constexpr int NC = CompGeom<F32>::NC, UC = CompGeom<F32>::UF + CompGeom<F32>::UL;
+                constexpr int NC = CompGeom<F32>::NC, UC = comp_chunk_units<F32>(COMP_SIGN);
                 for (int cc = 0; cc < NC; ++cc) {
-                    const long u = (long)(comp_unit_ptr<F32>(nullptr, cc, (int)h) - (const u4v *)nullptr);
-                    CHECK(u >= 0 && u + (UC - 1) * 64 < comp_units_total(F32, vh), "compressed FP32 unit of site %ld", h);
+                    const long u = (long)(comp_unit_ptr<F32, COMP_SIGN>(nullptr, cc, (int)h) - (const u4v *)nullptr);
+                    CHECK(u >= 0 && u + (UC - 1) * 64 < comp_units_total(F32, vh, COMP_SIGN),
+                          "compressed FP32 unit of site %ld", h);
                 }
                 const long tiles = (vh + LINK_TILE - 1) / LINK_TILE;
-                CHECK((long)(tiles * comp_units_per_site(F32) * 1024) + 4 * (h + 1) <= (long)link_parity_bytes(F32, vh, true),
+                CHECK((long)(tiles * comp_units_per_site(F32, COMP_SIGN) * 1024) + 4 * (h + 1) <=
+                          (long)link_parity_bytes(F32, vh, COMP_SIGN),
                       "FP32 sign word of site %ld", h);
             }
             {
-                constexpr int NC = CompGeom<H16>::NC, UC = CompGeom<H16>::UF + CompGeom<H16>::UL;
+                constexpr int NC = CompGeom<H16>::NC, UC = comp_chunk_units<H16>(COMP_SIGN);
                 for (int cc = 0; cc < NC; ++cc) {
-                    const long u = (long)(comp_unit_ptr<H16>(nullptr, cc, (int)h) - (const u4v *)nullptr);
-                    CHECK(u >= 0 && u + (UC - 1) * 64 < comp_units_total(H16, vh), "compressed FP16 unit of site %ld", h);
+                    const long u = (long)(comp_unit_ptr<H16, COMP_SIGN>(nullptr, cc, (int)h) - (const u4v *)nullptr);
+                    CHECK(u >= 0 && u + (UC - 1) * 64 < comp_units_total(H16, vh, COMP_SIGN),
+                          "compressed FP16 unit of site %ld", h);
+                }
+            }
+            {
+                constexpr int NC = CompGeom<F32>::NC, UC = comp_chunk_units<F32>(COMP_KAPPA);
+                static_assert(UC == 16, "FP32 kappa chunk: 9 fat + 6 long + 1 kappa unit");
+                for (int cc = 0; cc < NC; ++cc) {
+                    const long u = (long)(comp_unit_ptr<F32, COMP_KAPPA>(nullptr, cc, (int)h) - (const u4v *)nullptr);
+                    // the kernel reads units 0 .. 15 of the chunk (kappa at 15)
+                    CHECK(u >= 0 && u + 15 * 64 < comp_units_total(F32, vh, COMP_KAPPA),
+                          "kappa-compressed FP32 unit of site %ld", h);
+                }
+            }
+            {
+                constexpr int NC = CompGeom<H16>::NC, UC = comp_chunk_units<H16>(COMP_KAPPA);
+                static_assert(UC == 16, "FP16 kappa chunk: 9 fat + 6 long + 1 kappa unit");
+                for (int cc = 0; cc < NC; ++cc) {
+                    const long u = (long)(comp_unit_ptr<H16, COMP_KAPPA>(nullptr, cc, (int)h) - (const u4v *)nullptr);
+                    CHECK(u >= 0 && u + 15 * 64 < comp_units_total(H16, vh, COMP_KAPPA),
+                          "kappa-compressed FP16 unit of site %ld", h);
                 }
             }
         }

@@ -55,7 +55,7 @@ def test_params_default(lib):
     from paper_2111_10354_amd import hisq
     p = hisq.solver_params()
     assert p.tol == 1e-10 and p.max_iter == 100000 and p.ru_period == 100
-    assert p.sloppy_prec == hisq.PREC_FP64 and p.fallback == 1
+    assert p.sloppy_prec == hisq.PREC_FP64 and p.fallback == 1 and p.ru_delta == 0.1
 
 
 def test_invalid_arguments_rejected_without_gpu():
@@ -98,7 +98,29 @@ def test_header_layout_constants_match_binding():
     assert int(consts["HISQ_PREC_FP16S"]) == hisq.PREC_FP16S
     assert int(consts["HISQ_ERR_INVALID"]) == hisq.ERR_INVALID
     assert int(consts["HISQ_NOT_CONVERGED"]) == hisq.NOT_CONVERGED
-    assert C.sizeof(hisq.SolverParams) == 40 and C.sizeof(hisq.SolverStats) == 40
+
+
+@pytest.mark.parametrize("struct,cls", [("hisq_solver_params", "SolverParams"),
+                                        ("hisq_solver_stats", "SolverStats")])
+def test_struct_layout_matches_the_c_compiler(tmp_path, struct, cls):
+    """The ctypes mirrors of the host structs have the size and field offsets that
+    a C compiler gives the header's declarations."""
+    import shutil
+    import subprocess
+    from paper_2111_10354_amd import hisq
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    py = getattr(hisq, cls)
+    names = [f for f, _ in py._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("%zu\\n", offsetof({struct}, {n}));\n' for n in names)
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"hisq.h\"\n"
+                   f"int main(void) {{\n    printf(\"%zu\\n\", sizeof({struct}));\n{body}    return 0;\n}}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got[0] == C.sizeof(py)
+    assert got[1:] == [getattr(py, n).offset for n in names]
 
 
 def test_layout_helpers_roundtrip():
@@ -179,6 +201,11 @@ def test_coefficient_scalar_outputs_must_not_alias_the_arrays():
             assert "overlap" in hisq.last_error()
         assert fn(*args, n, C.byref(a0), al, sh, C.byref(dl)) == hisq.OK
         assert dl.value > 0 and all(v > 0 for v in sh)
+        # neighbours in one buffer are not overlaps: delta | alpha[n] | alpha0 | shift[n]
+        buf = (C.c_double * (2 * n + 2))()
+        assert fn(*args, n, elem(buf, n + 1), elem(buf, 1), elem(buf, n + 2), elem(buf, 0)) == hisq.OK, \
+            hisq.last_error()
+        assert buf[0] == pytest.approx(dl.value) and list(buf[n + 2:]) == pytest.approx(list(sh))
 
 
 def test_binding_rejects_undersized_buffers_before_any_call():

@@ -73,23 +73,28 @@ def test_dslash_matches_oracle(gauges, dims, prec, parity, full):
 
 
 def test_compression_choice(gauges, cuda_device):
-    """Long links are compressed exactly when every one is unitary with det +-1."""
-    import torch
+    """Long links are compressed with a sign bit exactly when every one is
+    unitary with det +-1, with a complex factor when every one is a positive
+    multiple of a unitary matrix, and not at all otherwise."""
     dims = (4, 4, 4, 4)
     g, F, L = gauges(dims)
-    assert g.compressed
+    assert g.comp_mode == 1
     g2, _, _ = gauges(dims, apbc=True)
-    assert g2.compressed  # boundary signs make det = -1, still compressible
+    assert g2.comp_mode == 1  # boundary signs make det = -1, still a sign bit
     gf, _, _ = gauges(dims, free=(9 / 8, -1 / 24))
-    assert not gf.compressed  # L = c3 eta: not unitary
-    L2 = np.array(L)
-    L2[17, 2] *= 1.0 + 1e-9  # one long link slightly off the unitary group
-    gp = make_gauge(dims, F, L2)
-    assert not gp.compressed
+    assert gf.comp_mode == 2  # L = c3 eta 1: a multiple of a unitary matrix
     chi = synth.gaussian_source(dims, 99, 1, parity=1)[0]
-    got, want = run_dslash(gp, dims, F, L2, chi, 0, "fp64")
-    assert rel_l2(got, want) <= TOL["fp64"]
-    gp.close()
+    L2 = np.array(L)
+    L2[17, 2] *= 1.0 + 1e-9  # one long link scaled: a multiple of a unitary matrix
+    L3 = np.array(L)
+    L3[17, 2, 0, 1] += 1e-9  # one entry moved off the unitary group
+    for Lx, mode in ((L2, 2), (L3, 0)):
+        gp = make_gauge(dims, F, Lx)
+        assert gp.comp_mode == mode
+        for prec in ("fp64", "fp32"):
+            got, want = run_dslash(gp, dims, F, Lx, chi, 0, prec)
+            assert rel_l2(got, want) <= TOL[prec]
+        gp.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
@@ -188,9 +193,9 @@ def test_multi_rhs_shifted_epilogue(gauges, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 def test_ragged_rhs_tiles(tmp_path, cuda_device, prec, full):
     """17 RHS in tiles of 2, 4, 8 and 16 (the last tile ragged: its missing RHS
-    repeat the last one and are never stored), plain and with the (A + sigma_i)
-    epilogue: every tile writes exactly what one RHS per thread writes, and
-    nothing beyond the 17 outputs."""
+    repeat the last one and are never stored), also split over several waves of
+    a workgroup, plain and with the (A + sigma_i) epilogue: every shape writes
+    exactly what one RHS per thread writes, and nothing beyond the 17 outputs."""
     import torch
     dims = (10, 6, 4, 8)
     F, L = fields(dims)
@@ -224,6 +229,12 @@ def test_ragged_rhs_tiles(tmp_path, cuda_device, prec, full):
         got, got_e = run((tile, 128, 0))
         assert np.array_equal(got, ref), tile
         assert np.array_equal(got_e, ref_e), tile
+    # RHS tiles of a site split over 2 or 4 waves of a workgroup (bits 24-25 of
+    # the order), the last workgroup's waves partly past the 17th RHS
+    for tile, block, rsl in ((1, 128, 1), (1, 256, 2), (2, 256, 1), (4, 256, 2), (2, 256, 2)):
+        got, got_e = run((tile, block, rsl << 24))
+        assert np.array_equal(got, ref), (tile, block, rsl)
+        assert np.array_equal(got_e, ref_e), (tile, block, rsl)
     for i in range(n):
         chi_q = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 1)
         want = to_cb(dims, oracle.dslash(dims, F, L, chi_q, 0), 0)

@@ -17,7 +17,9 @@ from layout import decode, encode, from_cb, rel_l2, to_cb
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
-RES_SLACK = 1.0 + 1e-3  # oracle's recomputation differs only by rounding
+# the solvers stop at 0.9 tol on their own FP64 residual, a margin for the
+# rounding of another evaluation: the oracle's recomputation meets tol itself
+RES_SLACK = 1.0
 
 
 @pytest.fixture(scope="module")
@@ -106,10 +108,10 @@ def test_mixed_precision_very_low_mass(sloppy):
     flush(f"iterations plain {st0[0]['iterations']}, {sloppy} {st[0]['iterations']}, "
           f"reliable updates {st[0]['reliable_updates']}")
     assert rc0 == 0 and rc == 0, st
-    # two FP64 evaluations of b - A x differ by ~ eps |A| |x| ~ 1e-16 x 1e5 |b|
-    # here (|x| is dominated by modes near 4 m^2 = 1.6e-5), i.e. ~10 % of the
-    # 1e-10 target: the oracle's recomputation gets that slack
-    assert oracle.true_residual(dims, F, L, mass, b, x) <= TOL * 1.1
+    # two FP64 evaluations of b - A x differ by rounding of order eps |A| |x|,
+    # large here (|x| is dominated by modes near 4 m^2 = 1.6e-5); the solver's
+    # 10 % margin covers it
+    assert oracle.true_residual(dims, F, L, mass, b, x) <= TOL * RES_SLACK
     # FP16S loses much of the Krylov space's orthogonality at this condition
     # number (measured ~9x the plain iteration count); only a runaway fails
     assert st[0]["iterations"] <= 12 * st0[0]["iterations"]
@@ -161,8 +163,11 @@ def test_free_field_solve_closed_form():
     g.close()
 
 
-@pytest.mark.parametrize("nshift", [4, 12])
-def test_multishift(c1, nshift):
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+@pytest.mark.parametrize("nshift", [1, 4, 12])
+def test_multishift(c1, nshift, sloppy):
+    """FP64 multi-shift, and the mixed form (FP32 Krylov iteration, FP64
+    reliable updates of the base, FP32-sloppy refinement of every shift)."""
     import torch
     dims, F, L, g = c1
     mass = 0.05
@@ -171,8 +176,8 @@ def test_multishift(c1, nshift):
     bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
     vh = synth.volume(dims) // 2
     x = torch.zeros(nshift * 48 * vh, dtype=torch.uint8, device="cuda")
-    flush(f"multishift 8^4 nshift={nshift}")
-    rc, st = hisq().multishift_cg(g, mass, list(shifts), bd, x)
+    flush(f"multishift 8^4 nshift={nshift} {sloppy}")
+    rc, st = hisq().multishift_cg(g, mass, list(shifts), bd, x, hisq().solver_params(sloppy_prec=sloppy))
     assert rc == 0, st
     xs = to_host(x).reshape(nshift, -1)
     for k, s in enumerate(shifts):
@@ -182,7 +187,8 @@ def test_multishift(c1, nshift):
         assert st[k]["true_residual"] <= TOL
 
 
-def test_multishift_unsorted_shifts(c1):
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+def test_multishift_unsorted_shifts(c1, sloppy):
     import torch
     dims, F, L, g = c1
     mass = 0.1
@@ -191,7 +197,8 @@ def test_multishift_unsorted_shifts(c1):
     bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
     vh = synth.volume(dims) // 2
     x = torch.zeros(len(shifts) * 48 * vh, dtype=torch.uint8, device="cuda")
-    rc, st = hisq().multishift_cg(g, mass, shifts, bd, x, hisq().solver_params(graph_chunk=0))
+    rc, st = hisq().multishift_cg(g, mass, shifts, bd, x,
+                                  hisq().solver_params(graph_chunk=0, sloppy_prec=sloppy))
     assert rc == 0
     xs = to_host(x).reshape(len(shifts), -1)
     for k, s in enumerate(shifts):
