@@ -4,11 +4,15 @@ to |r|/|b| < 1e-10, plain FP64 CG vs the mixed-precision form.
 One timed step = one FP32 single-parity Dslash over the whole 96^3 x 24
 lattice (one GPU's share of a large-volume HISQ lattice), 1 RHS, inputs
 resident in HBM.  Around it the run also measures the FP64 / FP16S /
-multi-RHS Dslash variants, CG solves at 32^3 x 8 (plain FP64 vs mixed
-FP32 and FP16S with reliable updates), batched, multi-shift and rational
-solves at 48^3 x 12, the network preconditioner, and - the CPU-baseline leg,
-the only one that runs the FP64 oracle - the oracle's own Dslash on the host
-cores, whose output is also compared with the timed launch's.
+multi-RHS Dslash variants, the 96^3 x 24 time to solution (plain FP64 CG
+against the chosen form: 4 RHS batched, mixed FP32/FP64), CG solves at
+32^3 x 8 (plain FP64 vs mixed FP32 and FP16S with reliable updates),
+batched, multi-shift and rational solves at 48^3 x 12, the network
+preconditioner, and - the CPU-baseline leg, the only one that runs the FP64
+oracle - the oracle's own Dslash on the host cores, whose output must match
+the timed launch's, and the oracle's true residual of every solution.
+
+Every workload's gauge field is generated before the GPU is first used.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -84,6 +88,72 @@ def time_launches(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms
 
 
+def generate_fields(which, dims_c5):
+    """Every workload's links, generated up front (before the GPU is used): the
+    worker pool forks only from a process without GPU state."""
+    import synth
+    out = {}
+    for name in which:
+        c = synth.CONFIGS[name]
+        dims = dims_c5 if name == "c5" else c["dims"]
+        t0 = time.time()
+        if name == "c5":  # the unfolded thin links too: the smearing leg starts from them
+            F, L, U = synth.fields.hisq_links_and_thin(dims, synth.CFG_IDS[name], c["eps"])
+            out[name], out["c5_thin"] = (F, L), U
+        else:
+            out[name] = synth.hisq_links(dims, synth.CFG_IDS[name], c["eps"], want_thin=(name == "c4"))
+        log(f"fields {name} {dims} (eps={c['eps']}): {time.time() - t0:.1f}s")
+    return out
+
+
+def run_smeared(hisq, torch, tune, dims, U, nrhs):
+    """HISQ smearing of the 96^3 x 24 thin links on the GPU, and the FP32 Dslash
+    on the smeared links (Naik links stored as two rows and a complex factor)."""
+    import synth
+    vh = synth.volume(dims) // 2
+    t = torch.from_numpy(U).cuda()
+    fat, lng = torch.empty_like(t), torch.empty_like(t)
+    hisq.smear_links(dims, t, fat, lng)  # first call: code objects loaded
+    torch.cuda.synchronize()
+    t1 = time.time()
+    hisq.smear_links(dims, t, fat, lng)
+    torch.cuda.synchronize()
+    t_smear = time.time() - t1
+    del t
+    g = hisq.Gauge(dims, fat, lng, ("fp32",))
+    del fat, lng
+    torch.cuda.empty_cache()
+    out = {"workload": f"{'x'.join(map(str, dims))}: HISQ smearing (fat7, U(3) projection, fat7 + Lepage, Naik) "
+                       "of the thin links in FP64, then the FP32 Dslash on the smeared links",
+           "smear_seconds": round(t_smear, 4), "naik_compression_mode": g.comp_mode}
+    real = 4
+    link = real * (8 * 18 + 8 * 12 + 8 * 2) if g.comp_mode == 2 else real * 16 * 18
+    for n in (1, nrhs):
+        hisq.autotune(g, "fp32", n, tune)
+        nb = hisq.spinor_bytes("fp32", vh) * n
+        i = torch.randn(nb // 4, device="cuda").view(torch.uint8)
+        o = torch.empty_like(i)
+        ms = time_launches(lambda: hisq.dslash_multi_rhs(g, 0, "fp32", n, i, o), 20, 5)
+        gbs = vh * (link + 2 * 24 * n) / (ms * 1e-3) / 1e9
+        out[f"fp32_x{n}rhs"] = {"ms": round(ms, 4), "gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                "shape": list(hisq.dslash_shape(g, "fp32", n, 0))}
+        log(f"smeared links: FP32 Dslash {n} RHS {ms:.3f} ms, {gbs:.0f} GB/s")
+        del i, o
+    log(f"smearing {dims}: {t_smear:.3f} s")
+    g.close()
+    return out
+
+
+def oracle_residuals(dims, F, L, mass, items):
+    """The oracle's FP64 true residual |b - (A + sigma) x| / |b| of every
+    (name, b, x, sigma) solution (full-lattice host vectors)."""
+    import oracle
+    out = {}
+    for name, b, x, sigma in items:
+        out[name] = oracle.true_residual(dims, F, L, mass, b, x, sigma=sigma)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,9 +162,10 @@ def main():
     # headline 2-4 % slow on some boxes
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--dims", type=str, default="96,96,96,24")
-    ap.add_argument("--quick", action="store_true", help="skip CG and the CPU baseline")
+    ap.add_argument("--quick", action="store_true", help="skip the solves and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 96^3x24 time to solution")
     ap.add_argument("--no-nn", action="store_true", help="skip the preconditioner network training and FCG")
     ap.add_argument("--c5-solve", action="store_true",
                     help="only the 96^3x24, m=0.002, 4-RHS solve: chosen form against plain FP64 CG (minutes)")
@@ -109,7 +180,7 @@ def main():
     ap.add_argument("--c3-solvers", action="store_true",
                     help="only the 48^3x12 solves (plain, mixed, 16-RHS batched, 12-shift, A^(-1/2))")
     ap.add_argument("--fields-cache", type=str, default=None,
-                    help="directory to save / reuse the generated link fields (profiling re-runs)")
+                    help="directory to save / reuse the generated 96^3x24 link fields (profiling re-runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -130,37 +201,51 @@ def main():
         sys.exit(2)
 
     import synth  # input generator only
+    tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
+    dims = tuple(int(v) for v in args.dims.split(","))
     if args.c3_solvers:
+        fl = generate_fields(("c3",), dims)
         import torch
         from paper_2111_10354_amd import hisq
-        tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
-        print(json.dumps(run_c3_solvers(hisq, torch, tune)), flush=True)
+        out, _ = run_c3_solvers(hisq, torch, tune, fl["c3"])
+        print(json.dumps(out), flush=True)
         return
     if args.c5_solve:
         # minutes-long solves: the library reports progress every 2000 iterations
         os.environ.setdefault("HISQ_SOLVER_TRACE", "1")
-        print(json.dumps(run_c5_solve(with_fp16s=args.c5_fp16s)), flush=True)
+        fl = generate_fields(("c5",), dims)
+        import torch
+        from paper_2111_10354_amd import hisq
+        out, _ = run_c5_solve(hisq, torch, tune, dims, *fl["c5"], with_fp16s=args.c5_fp16s)
+        print(json.dumps(out), flush=True)
         return
-    dims = tuple(int(v) for v in args.dims.split(","))
+
     V = synth.volume(dims)
     vh = V // 2
     cfg = synth.CONFIGS["c5"]
-    t0 = time.time()
+    full = not (args.quick or args.only_fp32)
+    want = ["c5"]
+    if full and not args.no_sweep or full and not (args.no_cg or args.no_c3):
+        want.append("c3")
+    if full and not args.no_cg:
+        want.append("c2")
+    if full and not args.no_nn:
+        want.append("c4")
     cache = None
     if args.fields_cache:
         tag = f"hisq_{'x'.join(map(str, dims))}_c5_eps{cfg['eps']}"
         cache = (os.path.join(args.fields_cache, tag + "_fat.npy"), os.path.join(args.fields_cache, tag + "_long.npy"))
     if cache and all(os.path.exists(p) for p in cache):
         log(f"loading cached fields {cache[0]}")
-        F, L = np.load(cache[0]), np.load(cache[1])
+        fields = {"c5": (np.load(cache[0]), np.load(cache[1]))}
+        fields.update(generate_fields([w for w in want if w != "c5"], dims))
     else:
-        log(f"generating fields {dims} (eps={cfg['eps']}) on {min(16, os.cpu_count() or 1)} workers")
-        F, L = synth.hisq_links(dims, synth.CFG_IDS["c5"], cfg["eps"])
+        fields = generate_fields(want, dims)
         if cache:
             os.makedirs(args.fields_cache, exist_ok=True)
-            np.save(cache[0], F)
-            np.save(cache[1], L)
-    log(f"fields ready in {time.time() - t0:.1f}s")
+            np.save(cache[0], fields["c5"][0])
+            np.save(cache[1], fields["c5"][1])
+    F, L = fields["c5"]
     chi = synth.gaussian_source(dims, synth.CFG_IDS["c5"], 1, parity=1)[0]
 
     import torch
@@ -169,7 +254,6 @@ def main():
     # every precision is packed even when only FP32 is timed, so that the
     # headline kernel's buffers sit where they sit in the default run
     precs = ("fp64", "fp32", "fp16s")
-    tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
 
     def make_gauge(full_links):
         fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
@@ -191,16 +275,20 @@ def main():
     g = make_gauge(True)
 
     cb, odd_sites = cb_gather(dims, chi, 1)
-    even_sites = cb_gather(dims, chi, 0)[1]
     bufs = {}
     for p in precs:
         inp = torch.from_numpy(encode(cb, p)).cuda()
         out = torch.empty(hisq.spinor_bytes(p, vh), dtype=torch.uint8, device="cuda")
         bufs[p] = (inp, out)
 
-    def algo_bytes(p, nrhs=1, comp=False):
+    def algo_bytes(p, nrhs=1, comp=0):
         real = {"fp64": 8, "fp32": 4, "fp16s": 2}[p]
-        link = real * (8 * 18 + 8 * 12) + 4 if comp and p != "fp64" else real * 16 * 18
+        if p == "fp64" or not comp:
+            link = real * 16 * 18
+        elif comp == 1:  # two rows + a sign word per site
+            link = real * (8 * 18 + 8 * 12) + 4
+        else:            # two rows + a complex factor per long link
+            link = real * (8 * 18 + 8 * 12 + 8 * 2)
         spin = {"fp64": 48, "fp32": 24, "fp16s": 16}[p]
         return vh * (link + nrhs * 2 * spin)
 
@@ -235,37 +323,62 @@ def main():
             o4 = torch.empty(hisq.spinor_bytes(p, vh) * n, dtype=torch.uint8, device="cuda")
             m4 = time_launches(lambda: hisq.dslash_multi_rhs(gx, 0, p, n, i4, o4), max(10, args.steps // 2), 3)
             key = f"{p}_x{n}rhs{suffix}"
-            variants[key] = {"ms": m4, "gbs": algo_bytes(p, n, comp=comp) / (m4 * 1e-3) / 1e9, "ms_per_rhs": m4 / n}
+            variants[key] = {"ms": m4, "gbs": algo_bytes(p, n, comp=comp) / (m4 * 1e-3) / 1e9, "ms_per_rhs": m4 / n,
+                             "shape": list(hisq.dslash_shape(gx, p, n, 0))}
             log(f"{key} Dslash: {m4:.3f} ms ({m4 / n:.3f} ms/RHS), {variants[key]['gbs']:.0f} GB/s")
             del i4, o4
 
+    c5 = None
+    solutions = {}
     if not args.only_fp32:
-        time_variants(g, False, "", True)
+        time_variants(g, 0, "", True)
         # long links as two rows + determinant sign (the layout the solvers use)
         g.close()
         torch.cuda.empty_cache()
         g = make_gauge(False)
         if g.compressed:
-            time_variants(g, True, "_compressed", False)
+            time_variants(g, g.comp_mode, "_compressed", False)
+        if not (args.quick or args.no_cg or args.no_c5):
+            c5, solutions["c5"] = run_c5_solve(hisq, torch, tune, dims, F, L, gauge=g)
     for k, v in variants.items():
         v["gflops"] = FLOP_PER_SITE * vh * (4 if "x4" in k else 1) / (v["ms"] * 1e-3) / 1e9
         v["frac_hbm_peak"] = v["gbs"] / HBM_PEAK_GBS
+    del bufs
+    g.close()
+    torch.cuda.empty_cache()
+    smeared = None
+    if full and "c5_thin" in fields:
+        smeared = run_smeared(hisq, torch, tune, dims, fields.pop("c5_thin"), cfg["nrhs"])
     sweep = None
-    if not (args.quick or args.no_sweep or args.only_fp32):
-        del bufs
-        g.close()
-        torch.cuda.empty_cache()
-        sweep = run_mrhs_sweep(hisq, torch, tune)
+    if full and not args.no_sweep:
+        sweep = run_mrhs_sweep(hisq, torch, tune, fields["c3"])
 
-    # ---- CPU baseline: the FP64 oracle's Dslash on this lattice, host cores
+    # ---- CG time to solution on the 32^3 x 8 workload
+    cg = None
+    if full and not args.no_cg:
+        cg, solutions["c2"] = run_cg(hisq, torch, fields["c2"])
+
+    # ---- batched and multi-shift solves on the 48^3 x 12 workload
+    c3 = None
+    if full and not (args.no_cg or args.no_c3):
+        c3, solutions["c3"] = run_c3_solvers(hisq, torch, tune, fields["c3"])
+
+    # ---- network preconditioner on the 32^3 x 8, m = 0.005 workload
+    nnres = None
+    if full and not args.no_nn:
+        nnres, solutions["c4"] = run_nn(hisq, torch, fields["c4"])
+
+    # ---- CPU baseline: the FP64 oracle's Dslash on this lattice, host cores;
+    # the timed launch's output and every solution checked by the oracle
     cpu = None
     perr = None
+    residuals = None
     if not (args.quick or args.no_cpu):
-        import oracle  # test infrastructure: the CPU baseline (and its check of the GPU output)
+        import oracle  # test infrastructure: the CPU baseline and the checks of the GPU results
         nthr = oracle.num_threads()
         log(f"oracle Dslash on the host ({nthr} threads)")
         reps, t_tot = 0, 0.0
-        while t_tot < 10.0 and reps < 20:
+        while t_tot < 2.0 and reps < 4:
             t1 = time.time()
             want = oracle.dslash(dims, F, L, chi, 0)
             t_tot += time.time() - t1
@@ -276,45 +389,40 @@ def main():
         perr = float(np.linalg.norm(got_fp32 - want_cb) / np.linalg.norm(want_cb))
         log(f"FP32 Dslash vs oracle over all {vh} output sites: rel L2 {perr:.2e}")
         del want, want_cb
+        if not perr <= 1e-6:
+            log(f"FAIL: the timed FP32 Dslash differs from the oracle by {perr:.2e} > 1e-6")
+            sys.exit(1)
         t_one = t_tot / reps
-        cpu = {"value": algo_bytes("fp64", comp=False) / t_one / 1e9, "unit": "GB/s", "cores": nthr, "kind": "oracle",
+        cpu = {"value": algo_bytes("fp64") / t_one / 1e9, "unit": "GB/s", "cores": nthr, "kind": "oracle",
                "sample": f"{reps} full single-parity FP64 Dslash applications on the same {dims} lattice "
                          f"({t_one:.2f} s each); GB/s counts the FP64 algorithmic bytes (2400 B/site)"}
         log(f"oracle: {t_one:.2f} s per Dslash = {cpu['value']:.2f} GB/s")
-        # the oracle's plain FP64 CG on the 32^3 x 8 workload: 200 iterations
-        # timed, the time to solution extrapolated to the GPU's iteration count
-        c2 = synth.CONFIGS["c2"]
-        F2, L2 = synth.hisq_links(c2["dims"], synth.CFG_IDS["c2"], c2["eps"])
-        b2 = synth.gaussian_source(c2["dims"], synth.CFG_IDS["c2"], 1, parity=0)[0]
+        if "c2" in fields:
+            # the oracle's plain FP64 CG on the 32^3 x 8 workload: 200 iterations
+            # timed, the time to solution extrapolated to the GPU's iteration count
+            c2 = synth.CONFIGS["c2"]
+            F2, L2 = fields["c2"]
+            b2 = synth.gaussian_source(c2["dims"], synth.CFG_IDS["c2"], 1, parity=0)[0]
+            t1 = time.time()
+            _, _, it2, _ = oracle.cg(c2["dims"], F2, L2, c2["mass"], b2, tol=1e-10, max_iter=200)
+            per_it = (time.time() - t1) / max(it2, 1)
+            cpu["cg_32x32x32x8"] = {"seconds_per_iteration": per_it, "iterations_timed": it2,
+                                    "note": "plain FP64 CG of the oracle; time to solution = this x the GPU's "
+                                            "plain-CG iteration count (extrapolated)"}
+            if cg is not None:
+                cpu["cg_32x32x32x8"]["extrapolated_seconds_to_solution"] = per_it * cg["plain_fp64"]["iterations"]
+            log(f"oracle CG 32^3x8: {1e3 * per_it:.1f} ms per iteration ({it2} timed)")
+        # the oracle's true residual of every solution of the run
+        residuals = {}
         t1 = time.time()
-        _, _, it2, _ = oracle.cg(c2["dims"], F2, L2, c2["mass"], b2, tol=1e-10, max_iter=200)
-        per_it = (time.time() - t1) / max(it2, 1)
-        cpu["cg_32x32x32x8"] = {"seconds_per_iteration": per_it, "iterations_timed": it2,
-                                "note": "plain FP64 CG of the oracle; time to solution = this x the GPU's "
-                                        "plain-CG iteration count (extrapolated)"}
-        log(f"oracle CG 32^3x8: {1e3 * per_it:.1f} ms per iteration ({it2} timed)")
-        del F2, L2
+        for name, (cdims, mass, items) in solutions.items():
+            Fx, Lx = fields[name][0], fields[name][1]
+            residuals[name] = oracle_residuals(cdims, Fx, Lx, mass, items)
+        worst = max((v for r in residuals.values() for v in r.values()), default=0.0)
+        residuals["worst"] = worst
+        log(f"oracle true residuals of {sum(len(r) for k, r in residuals.items() if k != 'worst')} solutions "
+            f"({time.time() - t1:.1f}s): worst {worst:.3e}")
     del F, L
-
-    # ---- CG time to solution on the 32^3 x 8 workload
-    cg = None
-    if not (args.quick or args.no_cg):
-        cg = run_cg(hisq, torch)
-        if cpu is not None and "cg_32x32x32x8" in cpu:
-            oc = cpu["cg_32x32x32x8"]
-            oc["extrapolated_seconds_to_solution"] = oc["seconds_per_iteration"] * cg["plain_fp64"]["iterations"]
-            log(f"oracle CG 32^3x8 extrapolated to {cg['plain_fp64']['iterations']} iterations: "
-                f"{oc['extrapolated_seconds_to_solution']:.1f} s (GPU plain FP64 {cg['plain_fp64']['seconds']:.3f} s)")
-
-    # ---- batched and multi-shift solves on the 48^3 x 12 workload
-    c3 = None
-    if not (args.quick or args.no_cg or args.no_c3):
-        c3 = run_c3_solvers(hisq, torch, tune)
-
-    # ---- network preconditioner on the 32^3 x 8, m = 0.005 workload
-    nnres = None
-    if not (args.quick or args.no_nn):
-        nnres = run_nn(hisq, torch)
 
     result = {
         "metric": METRIC,
@@ -339,6 +447,9 @@ def main():
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
         "cpu_baseline": cpu,
         "parity_rel_l2_vs_oracle": perr,
+        "oracle_true_residuals": residuals,
+        "time_to_solution_96x96x96x24": c5,
+        "smeared_links_96x96x96x24": smeared,
         "variants": variants,
         "cg": cg,
         "c3_solvers": c3,
@@ -346,21 +457,21 @@ def main():
     }
     result["config"]["launch_shape"] = {"rhs_tile": shape[0], "block": shape[1], "tile_order": shape[2]}
     result["mrhs_sweep"] = sweep
-    g.close()
     print(json.dumps(result), flush=True)
+    if residuals and not residuals["worst"] <= 1e-10:
+        log(f"FAIL: a reported solution's oracle true residual is {residuals['worst']:.3e} > 1e-10")
+        sys.exit(1)
 
 
-def run_mrhs_sweep(hisq, torch, tune):
+def run_mrhs_sweep(hisq, torch, tune, fields):
     """Multi-RHS Dslash on 48^3 x 12 (FP32 and FP16S): time per launch and per RHS
     for N = 1, 2, 4, 8, 16 with autotuned shapes."""
     import synth
     c = synth.CONFIGS["c3"]
     dims = c["dims"]
     vh = synth.volume(dims) // 2
-    log(f"multi-RHS sweep {dims}: generating fields")
-    F, L = synth.hisq_links(dims, synth.CFG_IDS["c3"], c["eps"])
+    F, L = fields
     g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp32", "fp16s"))
-    del F, L
     srcs = synth.gaussian_source(dims, synth.CFG_IDS["c3"], 16, parity=1)
     out = {"workload": f"{'x'.join(map(str, dims))} single-parity Dslash, N right-hand sides",
            "long_links_compressed": g.compressed, "fp32": {}, "fp16s": {}}
@@ -384,20 +495,30 @@ def run_mrhs_sweep(hisq, torch, tune):
     return out
 
 
-def run_cg(hisq, torch):
+def _host_solution(dims, xdev, vh, index=0):
+    """Full-lattice host vector of RHS `index` of an FP64 even-site solution stack."""
+    from paper_2111_10354_amd import layout
+    import synth
+    sb = 48 * vh
+    raw = xdev[index * sb:(index + 1) * sb].cpu().numpy()
+    full = np.zeros((synth.volume(dims), 3), np.complex128)
+    full[layout.parity_sites(dims, 0)] = layout.decode(raw, vh, "fp64").T
+    return full
+
+
+def run_cg(hisq, torch, fields):
     import synth
     c = synth.CONFIGS["c2"]
     dims, mass = c["dims"], c["mass"]
     vh = synth.volume(dims) // 2
-    log(f"CG workload {dims} m={mass}: generating fields")
-    F, L = synth.hisq_links(dims, synth.CFG_IDS["c2"], c["eps"])
+    F, L = fields
     g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32", "fp16s"))
     b = synth.gaussian_source(dims, synth.CFG_IDS["c2"], 1, parity=0)[0]
     bcb, _ = cb_gather(dims, b, 0)
     bd = torch.from_numpy(encode(bcb, "fp64")).cuda()
     out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, 1 Gaussian RHS, tol 1e-10 (true residual)"}
-    for name, sloppy in (("plain_fp64", "fp64"), ("mixed_fp32", "fp32"), ("mixed_fp16s", "fp16s"),
-                         ("mixed_fp16l", "fp16l")):
+    items = []
+    for name, sloppy in (("plain_fp64", "fp64"), ("mixed_fp32", "fp32"), ("mixed_fp16s", "fp16s")):
         prm = hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25)
         x = torch.zeros_like(bd)
         hisq.cg_solve(g, mass, 1, bd, x, hisq.solver_params(sloppy_prec=sloppy, graph_chunk=25, max_iter=50))
@@ -409,16 +530,16 @@ def run_cg(hisq, torch):
         out[name] = {"status": rc, "seconds": round(wall, 4), "iterations": st[0]["iterations"],
                      "reliable_updates": st[0]["reliable_updates"],
                      "true_residual": st[0]["true_residual"]}
+        items.append((name, b, _host_solution(dims, x, vh), 0.0))
         log(f"CG {name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
-    best = min(("mixed_fp32", "mixed_fp16s", "mixed_fp16l"),
-               key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
+    best = min(("mixed_fp32", "mixed_fp16s"), key=lambda k: out[k]["seconds"] if out[k]["status"] == 0 else 1e30)
     out["chosen"] = best
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
     g.close()
-    return out
+    return out, (dims, mass, items)
 
 
-def run_c3_solvers(hisq, torch, tune):
+def run_c3_solvers(hisq, torch, tune, fields):
     """48^3 x 12, m = 0.005: one RHS by plain FP64 CG and by mixed FP32 CG, all
     16 RHS batched through the multi-RHS Dslash (mixed FP32, FP64 reliable
     updates), the 12-shift ladder sigma_k = 10^(-4 + 4k/11) by multi-shift CG,
@@ -429,13 +550,12 @@ def run_c3_solvers(hisq, torch, tune):
     c = synth.CONFIGS["c3"]
     dims, mass, n, ns = c["dims"], c["mass"], c["nrhs"], c["nshift"]
     vh = synth.volume(dims) // 2
-    log(f"C3 solves {dims} m={mass}: generating fields")
-    F, L = synth.hisq_links(dims, synth.CFG_IDS["c3"], c["eps"])
-    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32", "fp16s"))
-    del F, L
-    for p in ("fp64", "fp32", "fp16l"):
-        for k in (1,) if p == "fp16l" else (1, n, ns):
+    F, L = fields
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32"))
+    for p in ("fp64", "fp32"):
+        for k in (1, n, ns):
             hisq.autotune(g, p, k, tune)
+    items = []
     srcs = synth.gaussian_source(dims, synth.CFG_IDS["c3"], n, parity=0)
     b = torch.from_numpy(np.concatenate([encode(cb_gather(dims, s_, 0)[0], "fp64") for s_ in srcs])).cuda()
     sb = hisq.spinor_bytes("fp64", vh)
@@ -456,12 +576,13 @@ def run_c3_solvers(hisq, torch, tune):
                 "true_residual_max": max(v["true_residual"] for v in st)}
 
     b0 = b[:sb]
-    for name, sloppy in (("plain_fp64_1rhs", "fp64"), ("mixed_fp32_1rhs", "fp32"), ("mixed_fp16l_1rhs", "fp16l")):
+    for name, sloppy in (("plain_fp64_1rhs", "fp64"), ("mixed_fp32_1rhs", "fp32")):
         x = torch.zeros_like(b0)
         (rc, st), wall = timed(lambda: hisq.cg_solve(g, mass, 1, b0, x, hisq.solver_params(sloppy_prec=sloppy)),
                                lambda: hisq.cg_solve(g, mass, 1, b0, torch.zeros_like(b0),
                                                      hisq.solver_params(sloppy_prec=sloppy, max_iter=50)))
         out[name] = summary(rc, st, wall, 1)
+        items.append((name, srcs[0], _host_solution(dims, x, vh), 0.0))
         log(f"C3 {name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
     for sl in ("fp32",):
         x = torch.zeros_like(b)
@@ -470,23 +591,30 @@ def run_c3_solvers(hisq, torch, tune):
                                                      hisq.solver_params(sloppy_prec=sl, max_iter=50)))
         key = f"batched_mixed_{sl}_{n}rhs"
         out[key] = summary(rc, st, wall, n)
+        items += [(f"{key}[{i}]", srcs[i], _host_solution(dims, x, vh, i), 0.0) for i in range(n)]
         log(f"C3 batched mixed {sl.upper()}, {n} RHS: {wall:.3f} s ({wall / n:.3f} s per RHS), "
             f"max {out[key]['iterations_max']} it, worst true res {out[key]['true_residual_max']:.2e}")
     shifts = [float(v) for v in synth.shifted_ladder(ns)]
-    xs = torch.zeros(ns * sb, dtype=torch.uint8, device="cuda")
-    (rc, st), wall = timed(lambda: hisq.multishift_cg(g, mass, shifts, b0, xs),
-                           lambda: hisq.multishift_cg(g, mass, shifts, b0, torch.zeros_like(xs),
-                                                      hisq.solver_params(max_iter=50)))
-    ms = summary(rc, st, wall, ns)
-    ms["shifts"] = shifts
-    ms["iterations_base"] = st[int(np.argmin(shifts))]["iterations"]
-    out[f"multishift_fp64_{ns}shifts"] = ms
-    log(f"C3 multi-shift, {ns} shifts: {wall:.3f} s, base {ms['iterations_base']} it, "
-        f"worst true res {ms['true_residual_max']:.2e}")
+    for sl in ("fp64", "fp32"):
+        xs = torch.zeros(ns * sb, dtype=torch.uint8, device="cuda")
+        prm = hisq.solver_params(sloppy_prec=sl)
+        (rc, st), wall = timed(lambda: hisq.multishift_cg(g, mass, shifts, b0, xs, prm),
+                               lambda: hisq.multishift_cg(g, mass, shifts, b0, torch.zeros_like(xs),
+                                                          hisq.solver_params(sloppy_prec=sl, max_iter=50)))
+        ms = summary(rc, st, wall, ns)
+        ms["shifts"] = shifts
+        items += [(f"multishift_{sl}[{k}]", srcs[0], _host_solution(dims, xs, vh, k), shifts[k]) for k in range(ns)]
+        ms["iterations_base"] = st[int(np.argmin(shifts))]["iterations"]
+        ms["iterations_per_shift"] = [v["iterations"] for v in st]
+        out[f"multishift_{sl}_{ns}shifts"] = ms
+        log(f"C3 multi-shift {sl.upper()}, {ns} shifts: {wall:.3f} s, base {ms['iterations_base']} it, "
+            f"worst true res {ms['true_residual_max']:.2e}")
     # rooted-staggered pseudofermions for two flavours on [4 m^2, 1.05 x the
     # power-iteration estimate of the top eigenvalue]: heat bath phi = A^(1/4) eta
     # (Remez coefficients), then the action phi^+ A^(-1/2) phi (Zolotarev), which
-    # returns |eta|^2 up to the two approximation errors
+    # returns |eta|^2 up to the two approximation errors; each with the FP64
+    # multi-shift and with the mixed one (FP32 Krylov iteration, FP32-sloppy
+    # refinement)
     t1 = time.time()
     lo, hi = hisq.spectral_bounds(g, mass, 100)
     t_bounds = time.time() - t1
@@ -494,39 +622,42 @@ def run_c3_solvers(hisq, torch, tune):
     t1 = time.time()
     h0, hal, hsh, hdelta = hisq.rational_remez(0.25, lo, 1.05 * hi, npole)
     t_remez = time.time() - t1
-    phi = torch.empty_like(b0)
-    (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, h0, hal, hsh, b0, phi),
-                           lambda: hisq.rational_apply(g, mass, h0, hal, hsh, b0, torch.empty_like(b0),
-                                                       hisq.solver_params(max_iter=50)))
-    out[f"heatbath_quarter_root_remez_{npole}poles"] = {
-        "status": rc, "seconds": round(wall, 4), "remez_seconds": round(t_remez, 4),
-        "approximation_rel_error": hdelta, "iterations_base": st[0]["iterations"],
-        "true_residual_max": max(v["true_residual"] for v in st)}
-    log(f"C3 heat bath A^(1/4) eta, {npole} Remez poles (rel. error {hdelta:.1e}, coefficients {t_remez:.3f} s): "
-        f"{wall:.3f} s, base {st[0]['iterations']} it")
     a0, al, sh, delta = hisq.zolotarev_inv_sqrt(lo, 1.05 * hi, npole)
-    y = torch.empty_like(b0)
-    (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, y),
-                           lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, torch.empty_like(b0),
-                                                       hisq.solver_params(max_iter=50)))
-    action = float(torch.dot(phi.view(torch.float64), y.view(torch.float64)))
     eta2 = float(torch.dot(b0.view(torch.float64), b0.view(torch.float64)))
-    out[f"inv_sqrt_zolotarev_{npole}poles"] = {
-        "status": rc, "seconds": round(wall, 4), "spectral_bounds": [lo, hi], "bounds_seconds": round(t_bounds, 4),
-        "approximation_rel_error": delta, "iterations_base": st[0]["iterations"],
-        "true_residual_max": max(v["true_residual"] for v in st), "pseudofermion_action": action,
-        "action_over_eta2_minus_1": action / eta2 - 1.0}
-    log(f"C3 action phi^+ A^(-1/2) phi, {npole} Zolotarev poles on [{lo:.2e}, {1.05 * hi:.3f}] (rel. error "
-        f"{delta:.1e}): {wall:.3f} s, base {st[0]['iterations']} it; S/|eta|^2 - 1 = {action / eta2 - 1:.1e}; "
-        f"bounds {t_bounds:.3f} s")
+    for sl in ("fp64", "fp32"):
+        sfx = "" if sl == "fp64" else "_mixed_fp32"
+        prm = hisq.solver_params(sloppy_prec=sl)
+        warm = hisq.solver_params(sloppy_prec=sl, max_iter=50)
+        phi = torch.empty_like(b0)
+        (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, h0, hal, hsh, b0, phi, prm),
+                               lambda: hisq.rational_apply(g, mass, h0, hal, hsh, b0, torch.empty_like(b0), warm))
+        out[f"heatbath_quarter_root_remez_{npole}poles{sfx}"] = {
+            "status": rc, "seconds": round(wall, 4), "remez_seconds": round(t_remez, 4),
+            "approximation_rel_error": hdelta, "iterations_base": st[0]["iterations"],
+            "true_residual_max": max(v["true_residual"] for v in st)}
+        log(f"C3 heat bath A^(1/4) eta ({sl} multi-shift), {npole} Remez poles (rel. error {hdelta:.1e}, "
+            f"coefficients {t_remez:.3f} s): {wall:.3f} s, base {st[0]['iterations']} it")
+        y = torch.empty_like(b0)
+        (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, y, prm),
+                               lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, torch.empty_like(b0), warm))
+        action = float(torch.dot(phi.view(torch.float64), y.view(torch.float64)))
+        out[f"inv_sqrt_zolotarev_{npole}poles{sfx}"] = {
+            "status": rc, "seconds": round(wall, 4), "spectral_bounds": [lo, hi],
+            "bounds_seconds": round(t_bounds, 4), "approximation_rel_error": delta,
+            "iterations_base": st[0]["iterations"], "true_residual_max": max(v["true_residual"] for v in st),
+            "pseudofermion_action": action, "action_over_eta2_minus_1": action / eta2 - 1.0}
+        log(f"C3 action phi^+ A^(-1/2) phi ({sl} multi-shift), {npole} Zolotarev poles on [{lo:.2e}, "
+            f"{1.05 * hi:.3f}] (rel. error {delta:.1e}): {wall:.3f} s, base {st[0]['iterations']} it; "
+            f"S/|eta|^2 - 1 = {action / eta2 - 1:.1e}; bounds {t_bounds:.3f} s")
     p1 = out["plain_fp64_1rhs"]["seconds"]
     out["speedup_batched_per_rhs_vs_plain"] = round(p1 / out[f"batched_mixed_fp32_{n}rhs"]["seconds_per_rhs"], 3)
+    ms = min((out[f"multishift_{sl}_{ns}shifts"] for sl in ("fp64", "fp32")), key=lambda v: v["seconds"])
     out["speedup_multishift_per_shift_vs_plain"] = round(p1 / ms["seconds_per_rhs"], 3)
     g.close()
-    return out
+    return out, (dims, mass, items)
 
 
-def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
+def run_nn(hisq, torch, fields, npairs=2048, batch=16, epochs=1, lr=3e-3):
     """Train the 1 -> 8 -> 8 -> 1 network on (A v, v) pairs generated on the GPU from
     this gauge field (v Gaussian from a seeded torch generator), then solve one
     Gaussian RHS with plain FP64 CG, mixed FP32 CG and flexible CG with the
@@ -535,11 +666,10 @@ def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
     c = synth.CONFIGS["c4"]
     dims, mass = c["dims"], c["mass"]
     vh = synth.volume(dims) // 2
-    log(f"network workload {dims} m={mass}: generating fields")
-    F, L, U = synth.hisq_links(dims, synth.CFG_IDS["c4"], c["eps"], want_thin=True)
+    F, L, U = fields
     g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32"))
     hisq.gauge_set_thin(g, torch.from_numpy(np.ascontiguousarray(U)).cuda())
-    del F, L, U
+    items = []
     diag = 4 * mass * mass
     chans = (1, 8, 8, 1)
     w0 = np.zeros(9 * (8 + 64 + 8), np.complex128)
@@ -603,6 +733,7 @@ def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
         wall = time.time() - t1
         out["solves"][name] = {"status": rc, "seconds": round(wall, 4), "iterations": st[0]["iterations"],
                                "fallback_used": st[0]["fallback_used"], "true_residual": st[0]["true_residual"]}
+        items.append((name, b, _host_solution(dims, x, vh), 0.0))
         log(f"{name}: {wall:.3f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
     sv = out["solves"]
     out["iterations_trained_over_plain"] = round(sv["fcg_trained"]["iterations"] / sv["plain_fp64"]["iterations"], 4)
@@ -611,31 +742,29 @@ def run_nn(hisq, torch, npairs=2048, batch=16, epochs=1, lr=3e-3):
     ident.close()
     net.close()
     g.close()
-    return out
+    return out, (dims, mass, items)
 
 
-def run_c5_solve(plain_rhs=1, with_fp16s=False):
+def run_c5_solve(hisq, torch, tune, dims, F, L, gauge=None, plain_rhs=1, with_fp16s=False):
     """(D^+D + 4m^2) x = b on 96^3 x 24, m = 0.002, 4 Gaussian RHS, tol 1e-10 on the
     FP64 true residual.  Plain form: FP64 CG one RHS at a time (timed on the
     first `plain_rhs` RHS; the 4-RHS total is that time per RHS x 4, marked as
-    such).  Chosen forms: the 4 RHS batched through the multi-RHS Dslash with
-    FP32 or (on request) FP16S sloppy iterations and FP64 reliable updates."""
-    import torch
+    such).  Chosen form: the 4 RHS batched through the multi-RHS Dslash with FP32
+    (or, on request, also FP16S) sloppy iterations and FP64 reliable updates.
+    `gauge`: a handle of these links with FP64, FP32 and FP16 copies (else one
+    is built here)."""
     import synth
-    from paper_2111_10354_amd import hisq
     c = synth.CONFIGS["c5"]
-    dims, mass, n = c["dims"], c["mass"], c["nrhs"]
+    mass, n = c["mass"], c["nrhs"]
     vh = synth.volume(dims) // 2
-    t0 = time.time()
-    F, L = synth.hisq_links(dims, synth.CFG_IDS["c5"], c["eps"])
-    log(f"C5 solve: fields {dims} in {time.time() - t0:.1f}s")
-    fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
-    g = hisq.Gauge(dims, fd, ld, ("fp64", "fp32", "fp16s"))
-    torch.cuda.synchronize()
-    del fd, ld, F, L
-    torch.cuda.empty_cache()
-    tune = os.path.join(ROOT, "paper_2111_10354_amd", "tuning", "gfx950.jsonl")
-    for p in ("fp64", "fp32", "fp16s"):
+    g = gauge
+    if g is None:
+        fd, ld = torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda()
+        g = hisq.Gauge(dims, fd, ld, ("fp64", "fp32", "fp16s"))
+        torch.cuda.synchronize()
+        del fd, ld
+        torch.cuda.empty_cache()
+    for p in ("fp64", "fp32") + (("fp16s",) if with_fp16s else ()):
         for k in (1, n):
             hisq.autotune(g, p, k, tune)
     srcs = synth.gaussian_source(dims, synth.CFG_IDS["c5"], n, parity=0)
@@ -643,6 +772,7 @@ def run_c5_solve(plain_rhs=1, with_fp16s=False):
     sb = hisq.spinor_bytes("fp64", vh)
     out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, {n} Gaussian RHS, tol 1e-10 (FP64 true residual)",
            "long_links_compressed": g.compressed}
+    items = []
     # plain form
     per = []
     for i in range(plain_rhs):
@@ -654,11 +784,14 @@ def run_c5_solve(plain_rhs=1, with_fp16s=False):
         wall = time.time() - t1
         per.append({"status": rc, "seconds": round(wall, 3), "iterations": st[0]["iterations"],
                     "true_residual": st[0]["true_residual"]})
+        items.append((f"plain_fp64[{i}]", srcs[i], _host_solution(dims, x, vh), 0.0))
         log(f"C5 plain FP64 RHS {i}: {wall:.1f} s, {st[0]['iterations']} it, true res {st[0]['true_residual']:.2e}")
+        del x
     mean = sum(r["seconds"] for r in per) / len(per)
     out["plain_fp64"] = {"per_rhs": per, "seconds_per_rhs": round(mean, 3),
                          "seconds_4rhs": round(mean * n, 3),
-                         "note": f"timed on {plain_rhs} of {n} RHS; total = per-RHS time x {n}"}
+                         "note": f"timed on {plain_rhs} of {n} RHS; the {n}-RHS total is the per-RHS time x {n} "
+                                 "(extrapolated)"}
     forms = (("batched_mixed_fp32", "fp32"),) + ((("batched_mixed_fp16s", "fp16s"),) if with_fp16s else ())
     for name, sloppy in forms:
         x = torch.zeros_like(b)
@@ -669,13 +802,16 @@ def run_c5_solve(plain_rhs=1, with_fp16s=False):
         out[name] = {"status": rc, "seconds_4rhs": round(wall, 3), "seconds_per_rhs": round(wall / n, 3),
                      "iterations": [s_["iterations"] for s_ in st],
                      "true_residual": [s_["true_residual"] for s_ in st]}
+        items += [(f"{name}[{i}]", srcs[i], _host_solution(dims, x, vh, i), 0.0) for i in range(n)]
         log(f"C5 {name}: {wall:.1f} s for {n} RHS, iterations {[s_['iterations'] for s_ in st]}, "
             f"worst true res {max(s_['true_residual'] for s_ in st):.2e}")
+        del x
     best = min((f for f, _ in forms), key=lambda k: out[k]["seconds_4rhs"] if out[k]["status"] == 0 else 1e30)
     out["chosen"] = best
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds_4rhs"] / out[best]["seconds_4rhs"], 3)
-    g.close()
-    return out
+    if gauge is None:
+        g.close()
+    return out, (dims, mass, items)
 
 
 if __name__ == "__main__":
