@@ -117,6 +117,7 @@ static int ws_alloc(CgWorkspace &w, const Geom &g, int n, int fmt) {
     if ((rc = w.diag.alloc(sizeof(double) * n))) return rc;
     if ((rc = w.scal.alloc(sizeof(double) * n))) return rc;
     w.n = n;
+    w.cap = n;
     w.fmt = fmt;
     return HISQ_OK;
 }
@@ -177,7 +178,8 @@ static int run_chunk(hisq_gauge_s *g, CgWorkspace &w, int chunk, bool use_graph,
         HISQ_HIP_CHECK(hipGetLastError());
         return HISQ_OK;
     }
-    if (!w.exec) {
+    auto &gr = w.graphs[w.n];
+    if (!gr.second) {
         hipStream_t cs = g->capture_stream;
         HISQ_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < chunk; ++i) {
@@ -188,11 +190,61 @@ static int run_chunk(hisq_gauge_s *g, CgWorkspace &w, int chunk, bool use_graph,
                 return rc;
             }
         }
-        HISQ_HIP_CHECK(hipStreamEndCapture(cs, &w.graph));
-        HISQ_HIP_CHECK(hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0));
+        HISQ_HIP_CHECK(hipStreamEndCapture(cs, &gr.first));
+        HISQ_HIP_CHECK(hipGraphInstantiate(&gr.second, gr.first, nullptr, nullptr, 0));
         w.chunk = chunk;
     }
-    HISQ_HIP_CHECK(hipGraphLaunch(w.exec, s));
+    HISQ_HIP_CHECK(hipGraphLaunch(gr.second, s));
+    return HISQ_OK;
+}
+
+// Compaction of a batched solve: once few enough RHS are still running, the
+// finished ones leave the batch (their solutions go to the
+// caller's x) and the running ones move to the lowest slots, so that the
+// multi-RHS Dslash and the vector kernels stop paying for finished RHS (a
+// Dslash workgroup runs as long as any RHS of its tile group is running).
+// slot_of[j] is the caller's index of slot j; hs holds the slots' states.
+static int cg_compact(hisq_gauge_s *g, CgWorkspace &w, std::vector<int> &slot_of, const std::vector<CgState> &hs,
+                      std::vector<CgState> &fin, const std::vector<double> &diag, double *x, hipStream_t s) {
+    const int vh = g->geom.vh, S = w.fmt;
+    const size_t s64 = spinor_bytes(F64, vh), s32 = spinor_bytes(F32, vh), sp = spinor_bytes(S, vh);
+    // a breakdown in mixed precision leaves a sloppy partial solution
+    if (S != F64) launch_accum_zero(F32, vh, w.n, w.x64.p, w.xs.p, w.st(), CG_BREAKDOWN, s);
+    auto cp = [&](DevBuf &b, size_t bytes, int to, int from) -> hipError_t {
+        return hipMemcpyAsync((char *)b.p + bytes * to, (char *)b.p + bytes * from, bytes, hipMemcpyDeviceToDevice,
+                              s);
+    };
+    std::vector<int> moved;
+    std::vector<double> dnew;
+    for (int j = 0; j < w.n; ++j) {
+        if (hs[j].flag != CG_RUNNING) {
+            HISQ_HIP_CHECK(hipMemcpyAsync((char *)x + s64 * slot_of[j], (char *)w.x64.p + s64 * j, s64,
+                                          hipMemcpyDeviceToDevice, s));
+            fin[slot_of[j]] = hs[j];
+            continue;
+        }
+        const int i = (int)moved.size();
+        if (i != j) {
+            HISQ_HIP_CHECK(cp(w.b64, s64, i, j));
+            HISQ_HIP_CHECK(cp(w.x64, s64, i, j));
+            if (S == F64) {
+                HISQ_HIP_CHECK(cp(w.r64, s64, i, j));
+                HISQ_HIP_CHECK(cp(w.p64, s64, i, j));
+            } else {
+                HISQ_HIP_CHECK(cp(w.xs, s32, i, j));
+                HISQ_HIP_CHECK(cp(w.rs, s32, i, j));
+                HISQ_HIP_CHECK(cp(w.ps, sp, i, j));
+            }
+            HISQ_HIP_CHECK(cp(w.state, sizeof(CgState), i, j));
+        }
+        moved.push_back(slot_of[j]);
+        dnew.push_back(diag[slot_of[j]]);
+    }
+    HISQ_HIP_CHECK(hipMemcpyAsync(w.diag.p, dnew.data(), sizeof(double) * dnew.size(), hipMemcpyHostToDevice, s));
+    // dnew is read by the copy engine before the next synchronisation
+    HISQ_HIP_CHECK(hipStreamSynchronize(s));
+    slot_of = moved;
+    w.n = (int)moved.size();
     return HISQ_OK;
 }
 
@@ -234,7 +286,14 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     CgWorkspace *wp = get_ws(g, n, S, LF, use_graph ? chunk : 0, &rc);
     if (!wp) return rc;
     CgWorkspace &w = *wp;
+    // compaction shrinks w.n during the solve; every exit restores it
+    struct RestoreN {
+        CgWorkspace &w;
+        ~RestoreN() { w.n = w.cap; }
+    } restore_n{w};
+    w.n = w.cap;
     const size_t s64 = spinor_bytes(F64, vh) * n;
+    const size_t sb = spinor_bytes(F64, vh);
 
     // coefficients and |b|
     std::vector<double> diag(n);
@@ -287,36 +346,64 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     // every pass either replays a chunk (at least one iteration of each running
     // RHS) or performs the reliable updates that the last chunk flagged
     const long max_chunks = 2L * prm.max_iter + 16;
+    std::vector<int> slot_of(n);  // caller's index of each slot
+    for (int i = 0; i < n; ++i) slot_of[i] = i;
+    std::vector<CgState> fin(n);  // final states, by the caller's index
     for (long c = 0; c < max_chunks; ++c) {
-        HISQ_HIP_CHECK(hipMemcpyAsync(hs.data(), w.state.p, sizeof(CgState) * n, hipMemcpyDeviceToHost, s));
+        const int m = w.n;
+        HISQ_HIP_CHECK(hipMemcpyAsync(hs.data(), w.state.p, sizeof(CgState) * m, hipMemcpyDeviceToHost, s));
         HISQ_HIP_CHECK(hipStreamSynchronize(s));
         if (trace) {
             int it = 0;
             double worst = 0.0;
-            for (int i = 0; i < n; ++i) {
+            for (int i = 0; i < m; ++i) {
                 it = std::max(it, hs[i].iter);
-                if (hs[i].flag != CG_DONE) worst = std::max(worst, std::sqrt(std::max(hs[i].rho, 0.0) / b2[i]));
+                if (hs[i].flag != CG_DONE)
+                    worst = std::max(worst, std::sqrt(std::max(hs[i].rho, 0.0) / b2[slot_of[i]]));
             }
             if (it >= next_report) {
-                std::fprintf(stderr, "[cg] iter %d, %d RHS, worst iterated |r|/|b| %.3e\n", it, n, worst);
+                std::fprintf(stderr, "[cg] iter %d, %d of %d RHS in the batch, worst iterated |r|/|b| %.3e\n", it,
+                             m, n, worst);
                 next_report = (it / 2000 + 1) * 2000;
             }
         }
-        bool attention = false, running = false;
-        for (auto &c2 : hs) {
-            attention |= c2.flag == CG_ATTENTION;
-            running |= c2.flag == CG_RUNNING;
+        bool attention = false;
+        int running = 0;
+        for (int i = 0; i < m; ++i) {
+            attention |= hs[i].flag == CG_ATTENTION;
+            running += hs[i].flag == CG_RUNNING;
         }
         if (attention) {
             if ((rc = cg_reliable(g, w, s))) return rc;
             continue;  // re-read the flags
         }
         if (!running) break;
+        // compact once the running RHS fit the next power of two below the
+        // batch (RHS tiles are powers of two)
+        int pow2 = 1;
+        while (2 * pow2 < m) pow2 *= 2;
+        if (running <= pow2 && running < m && (rc = cg_compact(g, w, slot_of, hs, fin, diag, x, s))) return rc;
         if ((rc = run_chunk(g, w, chunk, use_graph, s))) return rc;
     }
 
     // a breakdown in mixed precision leaves a sloppy partial solution
-    if (S != F64) launch_accum_zero(F32, vh, n, w.x64.p, w.xs.p, w.st(), CG_BREAKDOWN, s);
+    if (S != F64) launch_accum_zero(F32, vh, w.n, w.x64.p, w.xs.p, w.st(), CG_BREAKDOWN, s);
+    {
+        const int m = w.n;
+        HISQ_HIP_CHECK(hipMemcpyAsync(hs.data(), w.state.p, sizeof(CgState) * m, hipMemcpyDeviceToHost, s));
+        for (int j = 0; j < m; ++j)
+            HISQ_HIP_CHECK(hipMemcpyAsync((char *)x + sb * slot_of[j], (char *)w.x64.p + sb * j, sb,
+                                          hipMemcpyDeviceToDevice, s));
+        HISQ_HIP_CHECK(hipStreamSynchronize(s));
+        for (int j = 0; j < m; ++j) fin[slot_of[j]] = hs[j];
+    }
+    if (w.n != n) {
+        // back to the whole batch in the caller's order for the final residual
+        w.n = n;
+        HISQ_HIP_CHECK(hipMemcpyAsync(w.b64.p, b, s64, hipMemcpyDeviceToDevice, s));
+        HISQ_HIP_CHECK(hipMemcpyAsync(w.x64.p, x, s64, hipMemcpyDeviceToDevice, s));
+        HISQ_HIP_CHECK(hipMemcpyAsync(w.diag.p, diag.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    }
 
     // final FP64 true residual
     if ((rc = apply_A64(g, w, w.x64.p, w.ax64.p, s))) return rc;
@@ -324,9 +411,8 @@ int cg_solve(hisq_gauge_s *g, double mass, int n, const double *b, double *x, co
     launch_reduce(RED_STORE, n, (double *)w.part.p, blas_blocks(vh), nullptr, (double *)w.scal.p, s);
     std::vector<double> rr(n);
     HISQ_HIP_CHECK(hipMemcpyAsync(rr.data(), w.scal.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    HISQ_HIP_CHECK(hipMemcpyAsync(hs.data(), w.state.p, sizeof(CgState) * n, hipMemcpyDeviceToHost, s));
-    HISQ_HIP_CHECK(hipMemcpyAsync(x, w.x64.p, s64, hipMemcpyDeviceToDevice, s));
     HISQ_HIP_CHECK(hipStreamSynchronize(s));
+    hs = fin;
 
     const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     int worst = HISQ_OK;

@@ -98,15 +98,18 @@ struct DslashShape {
 // Buffers, device state and the captured iteration graph of one solver shape.
 struct CgWorkspace {
     int n = 0, fmt = F64, chunk = 0;
+    int cap = 0;     // RHS the buffers hold; n < cap while finished RHS are compacted out
     int lfmt = F64;  // links of the sloppy Dslash
     DevBuf b64, x64, r64, t64, ax64, p64, q64;
     DevBuf xs, rs, ps, ts, qs;
     DevBuf part, state, diag, scal;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // captured chunk of iterations per active RHS count
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     ~CgWorkspace() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (auto &kv : graphs) {
+            if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+            if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+        }
     }
     // sloppy views (aliases of the FP64 buffers in plain mode)
     void *X() { return fmt == F64 ? x64.p : xs.p; }

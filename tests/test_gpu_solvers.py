@@ -215,3 +215,40 @@ def test_invalid_shift_rejected(c1):
     with pytest.raises(hisq().HisqError) as e:
         hisq().multishift_cg(g, 0.1, [0.0, -0.05], b, x)
     assert e.value.code == hisq().ERR_INVALID
+
+
+@pytest.mark.parametrize("sloppy,graph_chunk", [("fp64", 16), ("fp32", 16), ("fp32", 0), ("fp16s", 16)])
+def test_batched_solve_compacts_finished_rhs(c1, sloppy, graph_chunk):
+    """Five RHS, three warm-started next to their solutions: those finish long
+    before the other two, the batch drops them (the two running ones fit a
+    smaller power-of-two batch) and moves the running ones to the front; every
+    solution must still reach the tolerance in the caller's order, with the
+    early ones' iteration counts."""
+    import torch
+    dims, F, L, g = c1
+    mass = 0.05
+    vh = synth.volume(dims) // 2
+    srcs = synth.gaussian_source(dims, 3, 5, parity=0, index0=70)
+    b = to_device(np.concatenate([encode(to_cb(dims, s, 0), "fp64") for s in srcs]))
+    rng = np.random.default_rng(5)
+    x0 = []
+    for i, s_ in enumerate(srcs):
+        if i in (0, 2, 3):
+            xo, _, _, _ = oracle.cg(dims, F, L, mass, s_, tol=1e-12)
+            xo = xo + 1e-6 * (rng.standard_normal(xo.shape) + 1j * rng.standard_normal(xo.shape))
+        else:
+            xo = np.zeros_like(s_)
+        x0.append(encode(to_cb(dims, xo, 0), "fp64"))
+    x = to_device(np.concatenate(x0))
+    flush(f"batched compaction 8^4 {sloppy} chunk={graph_chunk}")
+    rc, st = hisq().cg_solve(g, mass, 5, b, x, hisq().solver_params(sloppy_prec=sloppy, warm_start=1,
+                                                                    graph_chunk=graph_chunk))
+    assert rc == 0, st
+    xs = to_host(x).reshape(5, -1)
+    for i in range(5):
+        xi = from_cb(dims, decode(xs[i], vh, "fp64"), 0)
+        assert oracle.true_residual(dims, F, L, mass, srcs[i], xi) <= TOL, i
+        assert st[i]["true_residual"] <= TOL
+    early = max(st[i]["iterations"] for i in (0, 2, 3))
+    late = min(st[i]["iterations"] for i in (1, 4))
+    assert 2 * early < late, st
