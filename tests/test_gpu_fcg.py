@@ -158,16 +158,19 @@ def test_multishift_rejects_network(lat):
     net.close()
 
 
-def test_trained_network_gain(lat):
+def test_training_reaches_the_stencil_optimum_without_a_cg_gain(lat):
     """What training buys, against two fixed points the oracle computes on the same
     pairs: the best multiple of the identity and the best even-site stencil of the
     network's function class (identity plus the 56 two-hop paths, least squares).
     Training must close the gap between them from far above (the start is the
-    identity / 6, loss 3.4).  The flexible CG with the trained network is then
-    run against plain CG.  Measured: training lands on the stencil optimum, and
-    that optimum does not shorten the solve (2119 against 1788 iterations here;
-    the oracle's own FP64 flexible CG with the exact least-squares stencil needs
-    2056 against 1783), so the bound below only guards against regressions."""
+    identity / 6, loss 3.4).  The solve is then pinned on both sides: flexible CG
+    with the starting network (a multiple of the identity, plus 1e-3 noise)
+    must take plain CG's iteration count within 5 % (it iterates in FP32), and
+    with the trained network at most 1.25 times it.
+    Measured: 2119 (trained) against 1788 (plain), 1.19 times; the oracle's own
+    FP64 flexible CG with the exact least-squares stencil needs 2056 against
+    1783.  The network's optimum does not precondition A, so no gain is
+    asserted: the test guards the training and the solve cost."""
     import torch
     dims, F, L, U, g = lat
     mass, B = 0.02, 16
@@ -178,6 +181,7 @@ def test_trained_network_gain(lat):
     v_raw = np.concatenate([encode(to_cb(dims, v, 0), "fp32") for v in vs])
     q = lambda raw, i: from_cb(dims, decode(raw[i * 24 * vh:(i + 1) * 24 * vh], vh, "fp32"), 0)  # noqa: E731
     best, _, scalar = nn.stencil_optimum(dims, U, [(q(av_raw, i), q(v_raw, i)) for i in range(B)])
+    start = make_net(g, (1, 8, 8, 1), seed=2, noise=1e-3, scale=1.0 / (4 * mass * mass + 6.0))
     net = make_net(g, (1, 8, 8, 1), seed=2, noise=1e-3, scale=1.0 / (4 * mass * mass + 6.0))
     av_d, v_d = to_device(av_raw), to_device(v_raw)
     l0 = net.loss_grad(B, av_d, v_d, want_grad=False)[0]
@@ -193,13 +197,19 @@ def test_trained_network_gain(lat):
     rc, st, (x,) = fcg(g, dims, mass, [b], net)
     assert rc == 0, st
     check_solution(dims, F, L, mass, b, x, st[0])
+    rc0, st0, (x0,) = fcg(g, dims, mass, [b], start)
+    assert rc0 == 0, st0
+    check_solution(dims, F, L, mass, b, x0, st0[0])
     bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
     xd = torch.zeros_like(bd)
     rc2, st2 = hisq().cg_solve(g, mass, 1, bd, xd, hisq().solver_params())
     assert rc2 == 0
-    flush(f"iterations: flexible CG + trained network {st[0]['iterations']}, plain CG {st2[0]['iterations']}")
-    assert st[0]["iterations"] <= 1.5 * st2[0]["iterations"]
+    it_t, it_0, it_p = st[0]["iterations"], st0[0]["iterations"], st2[0]["iterations"]
+    flush(f"iterations: flexible CG + trained network {it_t}, + starting network {it_0}, plain CG {it_p}")
+    assert abs(it_0 - it_p) <= 0.05 * it_p, (it_0, it_p)
+    assert it_t <= 1.25 * it_p, (it_t, it_p)
     net.close()
+    start.close()
 
 
 def test_checkpoint_restores_the_network(lat, tmp_path):
