@@ -17,6 +17,8 @@
 // 1200 bytes (FP32), far below the ridge point, so it is written for memory
 // throughput on the vector ALUs; matrix cores would gain nothing here.
 
+#include <type_traits>
+
 #include "solver_internal.h"
 
 namespace hisq {
@@ -52,7 +54,12 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-template <int LF, int SI, int SO, int TILE, bool EPI, int CM, int RS>
+// XR (traversal order 3, RS = 1): the workgroup's sites are whole x-rows in
+// memory order; it stages the input colour vectors of those rows (its RHS
+// tile) in LDS, and the four x-direction hops of every site read LDS instead
+// of gathering through the caches.  A separate instance, so that the other
+// kernels keep their branch-free hop loops.
+template <int LF, int SI, int SO, int TILE, bool EPI, int CM, int RS, bool XR = false>
 __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restrict__ lptr, Spinor<SI> in,
                                                      Spinor<SO> out, Spinor<SI> y,
                                                      const double *__restrict__ diag,
@@ -74,6 +81,26 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
         for (int r = rb; r < rb + RS * TILE && r < nrhs; ++r)
             if (skip[r].flag == CG_RUNNING) idle = false;
         if (idle) return;  // uniform over the block
+    }
+
+    // x-row staging: thread t loads the input vectors of site base + t (the
+    // same row index in the input parity), for every RHS of its tile
+    extern __shared__ unsigned char xr_lds[];
+    cx<R> *xs = reinterpret_cast<cx<R> *>(xr_lds);  // [TILE][3][blockDim.x]
+    const int xbase = blk * (int)blockDim.x;
+    if constexpr (XR) {
+        static_assert(RS == 1, "x-row staging needs one wave per site");
+        if (h < g.vh) {
+#pragma unroll
+            for (int r = 0; r < TILE; ++r) {
+                const int rr = (TILE > 1 && r0 + r >= nrhs) ? nrhs - 1 : r0 + r;
+                cx<R> v[3];
+                in.rhs(rr).load(h, v);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xs[(r * 3 + c) * (int)blockDim.x + threadIdx.x] = v[c];
+            }
+        }
+        __syncthreads();
     }
 
     double part[TILE];
@@ -106,6 +133,20 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                     for (int b = 0; b < 3; ++b) cmac(acc[r][a], m[3 * a + b], v[b]);
             }
         };
+        // the same for an x-direction slot (k < 4) from the staged rows
+        auto apply_x = [&](int k, const cx<R> *m) {
+            const int li = hop_index(g, sc, h, 0, slot_dist(k & 3)) - xbase;
+#pragma unroll
+            for (int r = 0; r < TILE; ++r) {
+                cx<R> v[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) v[b] = xs[(r * 3 + b) * (int)blockDim.x + li];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) cmac(acc[r][a], m[3 * a + b], v[b]);
+            }
+        };
         // One RHS: every slot unrolled, the compiler interleaves the loads of
         // neighbouring slots.  Several RHS: one link group (or compressed
         // chunk) per loop trip with the gathers of all its RHS in flight
@@ -113,18 +154,27 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
         // spills them to scratch.
         if constexpr (CM == COMP_NONE) {
             const Links<LF, NT> links{lptr};
-            auto group = [&](int gi) {
+            // xd: the group's slots are x-direction hops read from the staged rows
+            auto group = [&](int gi, auto xd) {
                 cx<R> w[9 * G];
                 links.load_group(gi, h, w);
 #pragma unroll
-                for (int sl = 0; sl < G; ++sl) apply(gi * G + sl, w + 9 * sl);
+                for (int sl = 0; sl < G; ++sl) {
+                    if constexpr (decltype(xd)::value) apply_x(gi * G + sl, w + 9 * sl);
+                    else apply(gi * G + sl, w + 9 * sl);
+                }
             };
+            constexpr int GX = XR ? 4 / G : 0;  // groups of x-direction slots
             if constexpr (TILE == 1) {
 #pragma unroll
-                for (int gi = 0; gi < 16 / G; ++gi) group(gi);
+                for (int gi = 0; gi < GX; ++gi) group(gi, std::true_type{});
+#pragma unroll
+                for (int gi = GX; gi < 16 / G; ++gi) group(gi, std::false_type{});
             } else {
+#pragma unroll
+                for (int gi = 0; gi < GX; ++gi) group(gi, std::true_type{});
 #pragma unroll 1
-                for (int gi = 0; gi < 16 / G; ++gi) group(gi);
+                for (int gi = GX; gi < 16 / G; ++gi) group(gi, std::false_type{});
             }
         } else {
             // fat slots whole; long slots from rows 0, 1 and the determinant
@@ -133,12 +183,21 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
             const LinksC<LF, CM, NT> cl{lptr, g.vh};
             unsigned sg = 0;
             if constexpr (CM == COMP_SIGN) sg = cl.signs(h);
-            auto chunk = [&](int c) {
+            // xd: chunk 0, whose mu = 0 slots read the staged rows
+            auto chunk = [&](int c, auto xd) {
                 {
                     cx<R> w[18 * MC];
                     cl.load_fat(c, h, w);
 #pragma unroll
-                    for (int s2 = 0; s2 < 2 * MC; ++s2) apply(4 * (c * MC + (s2 >> 1)) + (s2 & 1), w + 9 * s2);
+                    for (int s2 = 0; s2 < 2 * MC; ++s2) {
+                        const int k = 4 * (c * MC + (s2 >> 1)) + (s2 & 1);
+                        if constexpr (decltype(xd)::value) {
+                            if (s2 < 2) apply_x(k, w + 9 * s2);  // s2 is unrolled: folded
+                            else apply(k, w + 9 * s2);
+                        } else {
+                            apply(k, w + 9 * s2);
+                        }
+                    }
                 }
                 {
                     cx<R> lr[12 * MC];
@@ -153,18 +212,25 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
                         for (int e = 0; e < 6; ++e) m[e] = lr[6 * s2 + e];
                         if constexpr (CM == COMP_KAPPA) rebuild_row2(m, kap[s2]);
                         else rebuild_row2(m, ((sg >> bit) & 1u) ? R(-1) : R(1));
-                        apply(4 * mu + 2 + (s2 & 1), m);
+                        if constexpr (decltype(xd)::value) {
+                            if (s2 < 2) apply_x(4 * mu + 2 + (s2 & 1), m);
+                            else apply(4 * mu + 2 + (s2 & 1), m);
+                        } else {
+                            apply(4 * mu + 2 + (s2 & 1), m);
+                        }
                     }
                 }
             };
             // (a chunk's fat and long slots in separate loop trips halve the
             // registers but measured 5-10 % slower: fewer gathers in flight)
+            constexpr int CX = XR ? 1 : 0;  // chunk 0 holds the x-direction slots
+            if constexpr (XR) chunk(0, std::true_type{});
             if constexpr (TILE == 1) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) chunk(c);
+                for (int c = CX; c < NC; ++c) chunk(c, std::false_type{});
             } else {
 #pragma unroll 1
-                for (int c = 0; c < NC; ++c) chunk(c);
+                for (int c = CX; c < NC; ++c) chunk(c, std::false_type{});
             }
         }
 
@@ -220,28 +286,46 @@ __global__ __launch_bounds__(256) void dslash_kernel(Geom g, const void *__restr
     }
 }
 
-template <int LF, int SI, int SO, int TILE, bool EPI, int RS>
-static void launch_rs(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+template <int LF, int SI, int SO, int TILE, bool EPI, int RS, bool XR>
+static void launch_xr(const Geom &g, const DslashLaunch &a, hipStream_t s) {
     dim3 block(a.block);
     const int ntiles = (a.nrhs + TILE - 1) / TILE;
     dim3 grid(dslash_grid_blocks(g, a.block, a.order), (ntiles + RS - 1) / RS);
+    const size_t lds = XR ? (size_t)TILE * 3 * a.block * 2 * sizeof(typename RealOf<LF>::T) : 0;
     Spinor<SI> in = spinor_view<SI>(const_cast<void *>(a.in), g.vh);
     Spinor<SO> out = spinor_view<SO>(a.out, g.vh);
     Spinor<SI> y = spinor_view<SI>(const_cast<void *>(a.y ? a.y : a.in), g.vh);
     if constexpr (LF != F64) {  // FP64 links are always stored whole
         if (a.compressed == COMP_SIGN) {
-            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_SIGN, RS>), grid, block, 0, s, g, a.links,
-                               in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_SIGN, RS, XR>), grid, block, lds, s, g,
+                               a.links, in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
             return;
         }
         if (a.compressed == COMP_KAPPA) {
-            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_KAPPA, RS>), grid, block, 0, s, g, a.links,
-                               in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+            hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_KAPPA, RS, XR>), grid, block, lds, s, g,
+                               a.links, in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
             return;
         }
     }
-    hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_NONE, RS>), grid, block, 0, s, g, a.links, in, out,
-                       y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+    hipLaunchKernelGGL((dslash_kernel<LF, SI, SO, TILE, EPI, COMP_NONE, RS, XR>), grid, block, lds, s, g, a.links,
+                       in, out, y, a.diag, a.partials, a.skip, a.parity, a.nrhs, a.order);
+}
+
+// LDS of the x-row staging per workgroup: TILE x 3 colours x block sites
+static size_t xrow_lds_bytes(int fl, int tile, int block) {
+    return (size_t)tile * 3 * block * 2 * (fl == F64 ? 8 : 4);
+}
+static constexpr size_t kXrowLdsMax = 64 * 1024;
+
+template <int LF, int SI, int SO, int TILE, bool EPI, int RS>
+static void launch_rs(const Geom &g, const DslashLaunch &a, hipStream_t s) {
+    if constexpr (RS == 1 && TILE <= 8) {
+        if ((order_tiles(a.order) & 0xff) == 3) {
+            launch_xr<LF, SI, SO, TILE, EPI, 1, true>(g, a, s);
+            return;
+        }
+    }
+    launch_xr<LF, SI, SO, TILE, EPI, RS, false>(g, a, s);
 }
 
 template <int LF, int SI, int SO, int TILE, bool EPI>
@@ -286,6 +370,9 @@ bool order_supported(const Geom &g, int order, int block) {
     if (order < 0 || (order >> 26)) return false;
     const int rs = order_rsplit(order);
     if (rs == 8 || block / rs < 64) return false;  // whole waves of sites
+    // x-row staging: one wave per site, workgroups of whole rows
+    if (order == 3) return (block == 64 || block == 128 || block == 192 || block == 256) && block % g.lxh == 0;
+    if (block != 64 && block != 128 && block != 256) return false;
     block /= rs;
     order = order_tiles(order);
     const int kind = order & 0xff;
@@ -302,12 +389,17 @@ bool order_supported(const Geom &g, int order, int block) {
 }
 
 int launch_dslash(const Geom &g, const DslashLaunch &a, hipStream_t s) {
-    if (a.block != 64 && a.block != 128 && a.block != 256) {
-        set_error("dslash: block size must be 64, 128 or 256");
+    const bool xrow = a.order == 3;
+    if (a.block != 64 && a.block != 128 && a.block != 256 && !(xrow && a.block == 192)) {
+        set_error("dslash: block size must be 64, 128 or 256 (or 192 with x-row staging)");
         return HISQ_ERR_INVALID;
     }
     if (!order_supported(g, a.order, a.block)) {
         set_error("dslash: traversal order not supported for this lattice");
+        return HISQ_ERR_INVALID;
+    }
+    if (xrow && (a.tile > 8 || xrow_lds_bytes(a.fmt_links, a.tile, a.block) > kXrowLdsMax)) {
+        set_error("dslash: x-row staging takes RHS tiles of at most 8 and 64 KiB of LDS");
         return HISQ_ERR_INVALID;
     }
     int rc = -1;

@@ -101,6 +101,9 @@ __host__ __device__ __forceinline__ constexpr int slot_dist(int j) { return j ==
 //    flight (+-1 and +-3 in every direction) fall inside a window of seven
 //    t-slices of the column, which is sized to stay in one L2; only the column
 //    faces are fetched twice.
+// 3: memory order with workgroups of whole x-rows (block a multiple of the
+//    row length Lx/2): the workgroup stages the input colour vectors of its
+//    rows in LDS and the four x-direction hops read them there.
 __host__ __device__ __forceinline__ int site_of_thread(const Geom &g, int blk, int nb, int bdim, int tid,
                                                        int order) {
     const int kind = order & 0xff;
@@ -108,7 +111,7 @@ __host__ __device__ __forceinline__ int site_of_thread(const Geom &g, int blk, i
     const int i = blk * bdim + tid;
     // grid tail: keep it out of range (the permutations below would map an
     // index past the last tile back onto a valid one)
-    if (kind == 0 || i >= g.vh) return i;
+    if (kind == 0 || kind == 3 || i >= g.vh) return i;
     const int tpp = (g.lxh * g.L[1]) >> 6;  // tiles per (z, t) plane
     int wt = i >> 6;
     if (kind == 1) {

@@ -1,9 +1,12 @@
 // Host-side check of the Dslash kernel's index arithmetic, built from the
 // kernel's own helpers (hisq_internal.h: site_of_thread, decode_site,
 // hop_index, link_unit_ptr, comp_unit_ptr are host + device).  For every
-// thread of the launch grids the kernel uses - block sizes 64, 128, 256, every
-// traversal order the launcher accepts - it checks that
+// thread of the launch grids the kernel uses - block sizes 64, 128, 256 (and
+// 192 with x-row staging), every traversal order the launcher accepts - it
+// checks that
 //  * the threads inside the lattice cover every output site exactly once;
+//  * with x-row staging, every x-direction hop stays inside the workgroup's
+//    own staged rows;
 //  * the decoded coordinates give back the site and its parity;
 //  * each of the 16 hops lands on the site a coordinate-based reference gives,
 //    of the other parity, inside [0, Vh);
@@ -43,6 +46,26 @@ static void check_lattice(const int dims[4], bool quick) {
         for (int bz : {2, 4, 8, 12, 16}) orders.push_back(2 | by << 8 | bz << 16);
     long launches = 0;
     for (int parity = 0; parity < 2; ++parity) {
+        // x-row staging (order 3): memory order, and every x-direction hop of a
+        // site inside the thread's own workgroup (the rows it staged in LDS)
+        for (int block : {64, 128, 192, 256}) {
+            if (!order_supported(g, 3, block)) continue;
+            ++launches;
+            const int nbs = dslash_grid_blocks(g, block, 3);
+            CHECK(nbs == (int)((vh + block - 1) / block), "x-row grid of %d blocks for block %d", nbs, block);
+            for (int blk = 0; blk < nbs; ++blk)
+                for (int tid = 0; tid < block; ++tid) {
+                    const int h = site_of_thread(g, blk, nbs, block, tid, 3);
+                    CHECK(h == blk * block + tid, "x-row order is not memory order at block %d", blk);
+                    if (h >= vh) continue;
+                    const SiteCoord sc = decode_site(g, h, parity);
+                    for (int k = 0; k < 4; ++k) {
+                        const int li = hop_index(g, sc, h, 0, slot_dist(k)) - blk * block;
+                        CHECK(li >= 0 && li < block && blk * block + li < vh,
+                              "x-row hop of site %d slot %d outside its workgroup (block %d)", h, k, block);
+                    }
+                }
+        }
         for (int block : {64, 128, 256}) {
             for (int base : orders)
             for (int rsl = 0; rsl <= 2; ++rsl) {
@@ -139,7 +162,8 @@ static void check_lattice(const int dims[4], bool quick) {
 
 int main(int argc, char **argv) {
     const int lattices[][4] = {{4, 4, 4, 4}, {6, 4, 4, 10}, {10, 6, 4, 8}, {8, 8, 8, 8}, {16, 8, 8, 8},
-                               {8, 12, 8, 16}, {16, 16, 16, 8}, {32, 32, 32, 8}, {48, 48, 48, 12}};
+                               {8, 6, 4, 10}, {12, 4, 4, 8}, {8, 12, 8, 16}, {16, 16, 16, 8}, {32, 32, 32, 8},
+                               {48, 48, 48, 12}};
     for (const auto &d : lattices) check_lattice(d, false);
     if (argc > 1) {  // the benchmark lattice: Vh = 10.6 M, one traversal order per kind
         const int big[4] = {96, 96, 96, 24};

@@ -339,3 +339,80 @@ def test_overlapping_stacks_rejected(gauges):
         with pytest.raises(H.HisqError) as e:
             call()
         assert e.value.code == H.ERR_INVALID and "overlap" in H.last_error(), i
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (12, 4, 4, 8)])
+@pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_xrow_staging_shapes(tmp_path, cuda_device, dims, prec, full):
+    """Traversal order 3: workgroups of whole x-rows stage their input colour
+    vectors in LDS and the x-direction hops read them there.  Every accepted
+    block size (whole rows; 8x6x4x10 has rows of 4 even sites and a last
+    workgroup past the lattice at block 256, 12x4x4x8 rows of 6, only block 192)
+    and RHS tile (9 RHS: ragged tiles) writes exactly what memory order with one
+    RHS per thread writes, plain and with the (A + sigma_i) epilogue, and
+    nothing past the outputs; the reference is checked against the oracle."""
+    import torch
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L, full_links=full)
+    vh = synth.volume(dims) // 2
+    lxh = dims[0] // 2
+    n = 9
+    diag = [0.04 + 0.03 * k for k in range(n)]
+    srcs = synth.gaussian_source(dims, 98, n, parity=1, index0=10)
+    raw = np.concatenate([encode(to_cb(dims, s, 1), prec) for s in srcs])
+    ys = synth.gaussian_source(dims, 98, n, parity=0, index0=20)
+    inp, y = to_device(raw), to_device(np.concatenate([encode(to_cb(dims, v, 0), prec) for v in ys]))
+    nb = spinor_nbytes(prec, vh)
+    guard = 4 * nb
+
+    def run(shape):
+        assert force_shape(g, prec, n, 0, shape, tmp_path / "p.jsonl") == shape
+        assert force_shape(g, prec, n, 1, shape, tmp_path / "e.jsonl") == shape
+        out = torch.full((nb * n + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+        epi = torch.full((nb * n + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+        hisq().dslash_multi_rhs(g, 0, prec, n, inp, out)
+        hisq().dslash_multi_rhs(g, 0, prec, n, inp, epi, diag=diag, y=y)
+        o, e = to_host(out), to_host(epi)
+        assert np.all(o[nb * n:] == 0x5A) and np.all(e[nb * n:] == 0x5A)
+        return o[:nb * n], e[:nb * n]
+
+    ref, ref_e = run((1, 64, 0))
+    tried = 0
+    for block in (64, 128, 192, 256):
+        if block % lxh:
+            continue
+        for tile in ((1, 2, 4) if prec == "fp64" else (1, 2, 4, 8)):
+            flush(f"x-row {dims} {prec} {'whole' if full else 'compressed'} tile {tile} block {block}")
+            got, got_e = run((tile, block, 3))
+            assert np.array_equal(got, ref), (tile, block)
+            assert np.array_equal(got_e, ref_e), (tile, block)
+            tried += 1
+    assert tried >= 3
+    for i in range(n):
+        chi_q = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 1)
+        want = to_cb(dims, oracle.dslash(dims, F, L, chi_q, 0), 0)
+        assert rel_l2(decode(ref[i * nb:(i + 1) * nb], vh, prec), want) <= TOL[prec]
+    g.close()
+
+
+def test_xrow_staging_in_a_batched_solve(tmp_path, cuda_device):
+    """A batched mixed FP32 solve whose Dslash launches use x-row staging."""
+    import torch
+    dims = (8, 8, 8, 8)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L)
+    mass, n = 0.05, 4
+    for epi in (0, 1):
+        assert force_shape(g, "fp32", n, epi, (2, 128, 3), tmp_path / f"s{epi}.jsonl") == (2, 128, 3)
+    srcs = synth.gaussian_source(dims, 99, n, parity=0, index0=80)
+    b = to_device(np.concatenate([encode(to_cb(dims, s, 0), "fp64") for s in srcs]))
+    x = torch.zeros_like(b)
+    rc, st = hisq().cg_solve(g, mass, n, b, x, hisq().solver_params(sloppy_prec="fp32"))
+    assert rc == 0, st
+    vh = synth.volume(dims) // 2
+    xs = to_host(x).reshape(n, -1)
+    for i in range(n):
+        xi = from_cb(dims, decode(xs[i], vh, "fp64"), 0)
+        assert oracle.true_residual(dims, F, L, mass, srcs[i], xi) <= 1e-10, i
+    g.close()
