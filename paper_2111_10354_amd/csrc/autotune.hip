@@ -137,6 +137,7 @@ static int shape_rsplit(const DslashShape &s) { return 1 << ((s.order >> 24) & 3
 static bool valid_shape(const Geom &geom, int fl, int nrhs, const DslashShape &s) {
     if (s.tile < 1 || s.tile > 16 || (s.tile & (s.tile - 1)) || s.tile > std::max(1, nrhs)) return false;
     if (fl == F64 && s.tile > 4) return false;
+    if ((s.order & 0xff) == 4 && s.tile > 4) return false;  // t-march: RHS tiles of up to 4
     if (s.order == 3) {  // x-row staging: RHS tiles of up to 8 in at most 64 KiB of LDS
         if (s.tile > 8 || (size_t)s.tile * 3 * s.block * 2 * (fl == F64 ? 8 : 4) > 64 * 1024) return false;
     } else if (s.block != 64 && s.block != 128 && s.block != 256) {
@@ -216,6 +217,16 @@ int tune_dslash(hisq_gauge_s *g, int fl, int fi, int fo, int nrhs, bool epi, con
                     c.tile = tile;
                     c.block = block;
                     c.order = order | rsl << 24;
+                    if (valid_shape(G, fl, nrhs, c)) cands.push_back(c);
+                }
+    for (int rsl = 0; rsl <= 2; ++rsl)  // t-march: K sites per thread along t
+        for (int tile : {1, 2, 4})
+            for (int block : {64, 128, 256})
+                for (int k = 1; k <= G.L[3] / 2; ++k) {
+                    DslashShape c;
+                    c.tile = tile;
+                    c.block = block;
+                    c.order = 4 | k << 8 | rsl << 24;
                     if (valid_shape(G, fl, nrhs, c)) cands.push_back(c);
                 }
     for (int tile : {1, 2, 4, 8})  // x-row staging (whole rows per workgroup, one wave per site)

@@ -104,6 +104,8 @@ __host__ __device__ __forceinline__ constexpr int slot_dist(int j) { return j ==
 // 3: memory order with workgroups of whole x-rows (block a multiple of the
 //    row length Lx/2): the workgroup stages the input colour vectors of its
 //    rows in LDS and the four x-direction hops read them there.
+// 4: t-march (K = bits 8-15 of `order`): each thread computes K sites of one
+//    (x, y, z) column, t advancing by 2 (tmarch_first_site below).
 __host__ __device__ __forceinline__ int site_of_thread(const Geom &g, int blk, int nb, int bdim, int tid,
                                                        int order) {
     const int kind = order & 0xff;
@@ -130,6 +132,18 @@ __host__ __device__ __forceinline__ int site_of_thread(const Geom &g, int blk, i
     wt /= g.L[3];
     const int yb = wt % nyb, zb = wt / nyb;
     return ((t * g.L[2] + zb * bz + zz) * tpp + yb * ty + within) * 64 + (i & 63);
+}
+
+// Order 4: thread i computes the K output sites h0, h0 + 2 st, ...,
+// h0 + 2 st (K - 1) of one (x, y, z) column, h0 = the value returned (Vh for
+// the grid tail).  The columns are the 2 st sites of t-slices 0 and 1;
+// consecutive threads take consecutive columns of one segment of K steps,
+// segment q covering t-slices 2 q K .. 2 q K + 2 K - 1.  K divides Lt / 2.
+__host__ __device__ __forceinline__ int tmarch_first_site(const Geom &g, int i, int K) {
+    const int cols = 2 * g.st;
+    if (i >= g.vh / K) return g.vh;
+    const int q = i / cols;
+    return (i - q * cols) + q * K * cols;
 }
 
 // ------------------------------------------------------------------ formats

@@ -7,6 +7,8 @@
 //  * the threads inside the lattice cover every output site exactly once;
 //  * with x-row staging, every x-direction hop stays inside the workgroup's
 //    own staged rows;
+//  * with the t-march, the K sites of every thread cover each output site
+//    once and each step stays in its (x, y, z) column;
 //  * the decoded coordinates give back the site and its parity;
 //  * each of the 16 hops lands on the site a coordinate-based reference gives,
 //    of the other parity, inside [0, Vh);
@@ -66,6 +68,41 @@ static void check_lattice(const int dims[4], bool quick) {
                     }
                 }
         }
+        // t-march (order 4, K sites per thread along t): the K sites of every
+        // thread of the grid, split over 1, 2, 4 waves, cover each output
+        // site exactly once
+        for (int k = 1; k <= dims[3] / 2; ++k)
+            for (int block : {64, 128, 256})
+                for (int rsl = 0; rsl <= 2; ++rsl) {
+                    const int order = 4 | k << 8 | rsl << 24, sb = block >> rsl;
+                    if (!order_supported(g, order, block)) continue;
+                    if (quick && (rsl || block != 128)) continue;
+                    ++launches;
+                    const int nbs = dslash_grid_blocks(g, block, order);
+                    CHECK(nbs == (int)((vh / k + sb - 1) / sb), "t-march grid of %d blocks (K %d block %d)", nbs, k,
+                          block);
+                    std::vector<unsigned char> seen(vh, 0);
+                    for (int blk = 0; blk < nbs; ++blk)
+                        for (int tid = 0; tid < sb; ++tid) {
+                            const int h0 = tmarch_first_site(g, blk * sb + tid, k);
+                            if (h0 >= vh) continue;
+                            for (int s = 0; s < k; ++s) {
+                                const long h = h0 + (long)s * 2 * g.st;
+                                CHECK(h >= 0 && h < vh, "t-march site %ld out of range (K %d)", h, k);
+                                if (h < 0 || h >= vh) continue;
+                                CHECK(!seen[h], "t-march site %ld twice (K %d block %d)", h, k, block);
+                                seen[h] = 1;
+                                if (s > 0) {  // the same column, two t-slices on
+                                    const SiteCoord a = decode_site(g, (int)(h - 2 * g.st), parity);
+                                    const SiteCoord b = decode_site(g, (int)h, parity);
+                                    CHECK(a.x == b.x && a.y == b.y && a.z == b.z && b.t == a.t + 2,
+                                          "t-march step of site %ld leaves its column", h);
+                                }
+                            }
+                        }
+                    for (long h = 0; h < vh; ++h)
+                        CHECK(seen[h], "t-march site %ld never visited (K %d block %d)", h, k, block);
+                }
         for (int block : {64, 128, 256}) {
             for (int base : orders)
             for (int rsl = 0; rsl <= 2; ++rsl) {

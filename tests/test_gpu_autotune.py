@@ -32,7 +32,7 @@ def test_autotune_keeps_output_and_caches(tmp_path, cuda_device, prec, nrhs):
     shape = hisq().dslash_shape(g, prec, nrhs, 0)
     order, rsplit = shape[2] & 0xffffff, 1 << ((shape[2] >> 24) & 3)
     assert shape[0] <= nrhs and shape[1] in ((64, 128, 192, 256) if order == 3 else (64, 128, 256))
-    assert order in (0, 1, 3) or order & 0xff == 2
+    assert order in (0, 1, 3) or order & 0xff in (2, 4)
     assert rsplit in (1, 2, 4) and shape[1] // rsplit >= 64 and shape[2] >> 26 == 0
     after = torch.empty_like(before)
     hisq().dslash_multi_rhs(g, 0, prec, nrhs, inp, after)

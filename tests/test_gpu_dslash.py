@@ -416,3 +416,82 @@ def test_xrow_staging_in_a_batched_solve(tmp_path, cuda_device):
         xi = from_cb(dims, decode(xs[i], vh, "fp64"), 0)
         assert oracle.true_residual(dims, F, L, mass, srcs[i], xi) <= 1e-10, i
     g.close()
+
+
+@pytest.mark.parametrize("dims", [(10, 6, 4, 8), (8, 6, 4, 10)])
+@pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_tmarch_shapes(tmp_path, cuda_device, dims, prec, full):
+    """Traversal order 4 (t-march): each thread computes K sites of one column,
+    t advancing by 2, with the t-direction inputs kept in registers.  Every K
+    dividing Lt/2 (10x6x4x8: 1, 2, 4; 8x6x4x10: 1, 5), RHS tile 1, 2, 4 (5 RHS:
+    ragged tiles) and split over 1 or 2 waves writes exactly what memory order
+    with one RHS per thread writes, plain and with the (A + sigma_i) epilogue,
+    and nothing past the outputs; the reference is checked against the oracle."""
+    import torch
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L, full_links=full)
+    vh = synth.volume(dims) // 2
+    n = 5
+    diag = [0.04 + 0.03 * k for k in range(n)]
+    srcs = synth.gaussian_source(dims, 98, n, parity=1, index0=30)
+    raw = np.concatenate([encode(to_cb(dims, s, 1), prec) for s in srcs])
+    ys = synth.gaussian_source(dims, 98, n, parity=0, index0=40)
+    inp, y = to_device(raw), to_device(np.concatenate([encode(to_cb(dims, v, 0), prec) for v in ys]))
+    nb = spinor_nbytes(prec, vh)
+    guard = 4 * nb
+
+    def run(shape):
+        assert force_shape(g, prec, n, 0, shape, tmp_path / "p.jsonl") == shape
+        assert force_shape(g, prec, n, 1, shape, tmp_path / "e.jsonl") == shape
+        out = torch.full((nb * n + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+        epi = torch.full((nb * n + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+        hisq().dslash_multi_rhs(g, 0, prec, n, inp, out)
+        hisq().dslash_multi_rhs(g, 0, prec, n, inp, epi, diag=diag, y=y)
+        o, e = to_host(out), to_host(epi)
+        assert np.all(o[nb * n:] == 0x5A) and np.all(e[nb * n:] == 0x5A)
+        return o[:nb * n], e[:nb * n]
+
+    ref, ref_e = run((1, 64, 0))
+    half = dims[3] // 2
+    tried = 0
+    for k in [k for k in range(1, half + 1) if half % k == 0]:
+        for tile, block, rsl in ((1, 64, 0), (2, 128, 0), (4, 256, 0), (1, 128, 1), (2, 256, 1)):
+            if prec == "fp64" and tile * (1 << rsl) > 4:
+                continue
+            shape = (tile, block, 4 | k << 8 | rsl << 24)
+            flush(f"t-march {dims} {prec} {'whole' if full else 'compressed'} K {k} tile {tile} block {block} "
+                  f"split {1 << rsl}")
+            got, got_e = run(shape)
+            assert np.array_equal(got, ref), shape
+            assert np.array_equal(got_e, ref_e), shape
+            tried += 1
+    assert tried >= 8
+    for i in range(n):
+        chi_q = from_cb(dims, decode(raw[i * nb:(i + 1) * nb], vh, prec), 1)
+        want = to_cb(dims, oracle.dslash(dims, F, L, chi_q, 0), 0)
+        assert rel_l2(decode(ref[i * nb:(i + 1) * nb], vh, prec), want) <= TOL[prec]
+    g.close()
+
+
+def test_tmarch_in_a_batched_solve(tmp_path, cuda_device):
+    """A batched mixed FP32 solve whose Dslash launches march along t."""
+    import torch
+    dims = (8, 8, 8, 8)
+    F, L = fields(dims)
+    g = make_gauge(dims, F, L)
+    mass, n = 0.05, 4
+    shape = (1, 128, 4 | 2 << 8 | 1 << 24)
+    for epi in (0, 1):
+        assert force_shape(g, "fp32", n, epi, shape, tmp_path / f"s{epi}.jsonl") == shape
+    srcs = synth.gaussian_source(dims, 99, n, parity=0, index0=90)
+    b = to_device(np.concatenate([encode(to_cb(dims, s, 0), "fp64") for s in srcs]))
+    x = torch.zeros_like(b)
+    rc, st = hisq().cg_solve(g, mass, n, b, x, hisq().solver_params(sloppy_prec="fp32"))
+    assert rc == 0, st
+    vh = synth.volume(dims) // 2
+    xs = to_host(x).reshape(n, -1)
+    for i in range(n):
+        xi = from_cb(dims, decode(xs[i], vh, "fp64"), 0)
+        assert oracle.true_residual(dims, F, L, mass, srcs[i], xi) <= 1e-10, i
+    g.close()
