@@ -35,7 +35,7 @@ MUTATIONS = [
 ]
 
 
-def run_pins(tmp_path, source):
+def run_pins(tmp_path, source, stop_first=False):
     tree = tmp_path / "tree"
     (tree / "tests").mkdir(parents=True)
     shutil.copytree(os.path.join(ROOT, "oracle"), tree / "oracle", ignore=shutil.ignore_patterns("__pycache__"))
@@ -44,8 +44,10 @@ def run_pins(tmp_path, source):
         shutil.copy(os.path.join(ROOT, "tests", f), tree / "tests" / f)
     (tree / "oracle" / "smear.py").write_text(source)
     env = dict(os.environ, OMP_NUM_THREADS="4", HISQ_ORACLE_LIB=os.path.join(ROOT, "oracle", "_hisq_oracle.so"))
+    # a mutant needs one failing pin: stop there
     return subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_smear.py", "-q", "-p",
-                           "no:cacheprovider"], cwd=tree, env=env, capture_output=True, text=True, timeout=600)
+                           "no:cacheprovider"] + (["-x"] if stop_first else []), cwd=tree, env=env,
+                          capture_output=True, text=True, timeout=600)
 
 
 def test_unchanged_copy_passes(tmp_path):
@@ -58,5 +60,5 @@ def test_unchanged_copy_passes(tmp_path):
 def test_pins_catch_planted_mistake(tmp_path, name, old, new):
     src = open(SRC).read()
     assert old in src, name
-    r = run_pins(tmp_path, src.replace(old, new, 1))
+    r = run_pins(tmp_path, src.replace(old, new, 1), stop_first=True)
     assert r.returncode == 1 and " failed" in r.stdout, f"no pin caught: {name}\n{r.stdout[-2000:]}"
