@@ -181,6 +181,11 @@ def main():
                     help="only the 48^3x12 solves (plain, mixed, 16-RHS batched, 12-shift, A^(-1/2))")
     ap.add_argument("--fields-cache", type=str, default=None,
                     help="directory to save / reuse the generated 96^3x24 link fields (profiling re-runs)")
+    ap.add_argument("--mrhs", type=int, default=0,
+                    help="only the N-RHS FP32 Dslash on the --dims lattice (long links compressed unless --full-links), "
+                         "for profiling: --shape forces a launch shape")
+    ap.add_argument("--shape", type=str, default=None, help="with --mrhs: tile,block,order")
+    ap.add_argument("--full-links", action="store_true", help="with --mrhs: store every link whole")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 4 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -209,6 +214,9 @@ def main():
         from paper_2111_10354_amd import hisq
         out, _ = run_c3_solvers(hisq, torch, tune, fl["c3"])
         print(json.dumps(out), flush=True)
+        return
+    if args.mrhs:
+        run_mrhs_only(args, dims, tune)
         return
     if args.c5_solve:
         # minutes-long solves: the library reports progress every 2000 iterations
@@ -537,6 +545,61 @@ def run_cg(hisq, torch, fields):
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
     g.close()
     return out, (dims, mass, items)
+
+
+def run_mrhs_only(args, dims, tune):
+    """One N-RHS FP32 Dslash shape on the benchmark lattice, timed with HIP events
+    (for counter runs: the launches of the timed loop are the last ones)."""
+    import synth
+    import torch
+    from paper_2111_10354_amd import hisq
+    n = args.mrhs
+    cache = None
+    if args.fields_cache:
+        cfg = synth.CONFIGS["c5"]
+        tag = f"hisq_{'x'.join(map(str, dims))}_c5_eps{cfg['eps']}"
+        cache = (os.path.join(args.fields_cache, tag + "_fat.npy"), os.path.join(args.fields_cache, tag + "_long.npy"))
+    if cache and all(os.path.exists(p) for p in cache):
+        F, L = np.load(cache[0]), np.load(cache[1])
+    else:
+        F, L = generate_fields(["c5"], dims)["c5"]
+        if cache:
+            os.makedirs(args.fields_cache, exist_ok=True)
+            np.save(cache[0], F)
+            np.save(cache[1], L)
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp32",),
+                   full_links=args.full_links)
+    del F, L
+    table = tune
+    if args.shape:
+        t, b, o = (int(v) for v in args.shape.split(","))
+        table = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"hisq_shape_{os.getpid()}.jsonl")
+        probe = table + ".probe"
+        hisq.autotune(g, "fp32", n, probe)  # writes this handle's keys
+        keys = [json.loads(line)["key"] for line in open(probe)]
+        with open(table, "w") as f:
+            for k in keys:
+                if f"|n{n}|e0" in k:
+                    f.write(json.dumps({"key": k, "tile": t, "block": b, "order": o, "ms": 0.0}) + "\n")
+        os.remove(probe)
+    hisq.autotune(g, "fp32", n, table)
+    shape = tuple(hisq.dslash_shape(g, "fp32", n, 0))
+    if args.shape:
+        os.remove(table)
+        assert shape == (t, b, o), (shape, args.shape)
+    vh = synth.volume(dims) // 2
+    nb = hisq.spinor_bytes("fp32", vh)
+    inp = torch.randn(n * nb // 4, device="cuda").view(torch.uint8)
+    out = torch.empty(n * nb, dtype=torch.uint8, device="cuda")
+    ms = time_launches(lambda: hisq.dslash_multi_rhs(g, 0, "fp32", n, inp, out), args.steps, args.warmup)
+    comp = g.comp_mode
+    link = 4 * 16 * 18 if comp == 0 else 4 * (8 * 18 + 8 * 12) + 4 if comp == 1 else 4 * (8 * 18 + 8 * 12 + 16)
+    gbs = vh * (link + n * 48) / (ms * 1e-3) / 1e9
+    log(f"{n}-RHS FP32 Dslash, shape {shape}: {ms:.4f} ms, {gbs:.0f} GB/s algorithmic")
+    print(json.dumps({"workload": f"{'x'.join(map(str, dims))} single-parity FP32 Dslash, {n} RHS",
+                      "long_links": ["whole", "sign", "kappa"][comp], "shape": shape, "ms": ms, "gbs": gbs,
+                      "steps": args.steps, "warmup": args.warmup}), flush=True)
+    g.close()
 
 
 def run_c3_solvers(hisq, torch, tune, fields):
