@@ -3,7 +3,9 @@ bench.py times (the shapes of the committed tuning table): the FP64, FP32 and
 FP16S Dslash on 96^3 x 24 with 1 and 4 right-hand sides, long links whole and
 compressed, and the 16-RHS Dslash on 48^3 x 12.  The oracle cannot apply the
 operator to 21 million sites in seconds, so every right-hand side is checked
-on 256 sampled output sites, which the oracle computes one by one; the
+on 256 random output sites plus ~150 sites on the lattice faces, where the
+fat and Naik hops wrap around (every direction, coordinates 0-2 and L-3 to
+L-1, and corners), which the oracle computes one by one; the
 tolerances are those of the small-lattice parity tests (FP64 1e-13, FP32 1e-6,
 FP16S 2e-3 relative L2 over the sample, the oracle fed the GPU's rounded
 input).
@@ -36,6 +38,35 @@ def tune(tmp_path_factory):
     return str(path)
 
 
+def face_sites(dims, rng, per_face=6):
+    """Even output sites (as parity indices h) where hops wrap around the
+    lattice: for every direction, sites whose coordinate is 0, 1, 2, L-3, L-2
+    or L-1 (the fat and Naik hops that cross the boundary), plus corners with
+    every coordinate on a face."""
+    L = np.array(dims)
+    edge = lambda n: np.array([0, 1, 2, n - 3, n - 2, n - 1])  # noqa: E731
+    pts = []
+    for mu in range(4):
+        for e in edge(dims[mu]):
+            for _ in range(per_face):
+                c = rng.integers(0, L)
+                c[mu] = e
+                pts.append(c)
+    for _ in range(16):
+        pts.append(np.array([rng.choice(edge(n)) for n in dims]))
+    hs = set()
+    for c in pts:
+        if c.sum() % 2:  # make it even: move along a direction other than the face's, inside the lattice
+            nu = int(np.argmax(L))
+            c[nu] = (c[nu] + 1) % dims[nu] if c[nu] not in (0, dims[nu] - 1) else c[nu] ^ 1
+            if c.sum() % 2:
+                c[0] = c[0] ^ 1
+        lex = c[0] + dims[0] * (c[1] + dims[1] * (c[2] + dims[2] * c[3]))
+        assert (c.sum() % 2) == 0
+        hs.add(int(lex) // 2)
+    return np.array(sorted(hs))
+
+
 def sampled_check(g, dims, F, L, prec, nrhs, seed, tune):
     import torch
     vh = synth.volume(dims) // 2
@@ -53,8 +84,9 @@ def sampled_check(g, dims, F, L, prec, nrhs, seed, tune):
     got = to_host(out).reshape(nrhs, -1)
     even = parity_sites(dims, 0)
     rng = np.random.default_rng(seed)
+    faces = face_sites(dims, rng)
     for i in range(nrhs):
-        hs = np.sort(rng.choice(vh, size=NSAMPLE, replace=False))
+        hs = np.union1d(rng.choice(vh, size=NSAMPLE, replace=False), faces)
         chi_q = from_cb(dims, decode(raw[i], vh, prec), 1)
         want = oracle.dslash_sites(dims, F, L, chi_q, even[hs])
         have = decode(got[i], vh, prec)[:, hs].T
