@@ -212,9 +212,12 @@ int hisq_dslash_multi_rhs_noalloc(hisq_gauge_t g, int out_parity, int prec, int 
 
 /*
  * Autotune the Dslash launch shape (RHS tile per thread: 1, 2, 4, 8 or 16, at
- * most 4 with FP64 links; block size 64, 128 or 256; order in which the
- * 64-site tiles are processed: memory order, t-fastest planes, or XCD bricks
- * 2 | BY << 8 | BZ << 16) for the kernels a solve in `prec`
+ * most 4 with FP64 links; block size 64, 128 or 256; order: bits 0-23 the
+ * traversal - 0 memory order, 1 t-fastest planes, 2 | BY << 8 | BZ << 16 XCD
+ * bricks, 3 memory order with the x-rows of a workgroup staged in LDS (block
+ * 64-256 threads of whole rows, tiles up to 8), 4 | K << 8 a t-march of K
+ * sites per thread (tiles up to 4) - and bits 24-25 log2 of the number of
+ * waves a site's RHS tiles are split over) for the kernels a solve in `prec`
  * with `nrhs` right-hand sides launches: plain and epilogue Dslash in `prec`
  * and, if FP64 links are packed, the FP64 kernels of the reliable updates.
  * Each candidate must write bit-identical output to the default shape before
