@@ -1,7 +1,6 @@
 // HISQ single-parity Dslash for gfx950, single- and multi-RHS.
 //
-// One thread owns one output site h (K sites of a column in the t-march
-// variant) and a tile of TILE right-hand sides.  For
+// One thread owns one output site h and a tile of TILE right-hand sides.  For
 // each of the 16 link slots it streams the 9 complex entries of the slot's
 // link once (non-temporal: each link is read exactly once per application and
 // must not evict the spinors that neighbouring sites still reuse), gathers the
