@@ -52,8 +52,11 @@ def test_inverse_sqrt_matches_dense(cuda_device):
     g.close()
 
 
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
 @pytest.mark.parametrize("full", [False, True], ids=["compressed", "full"])
-def test_partial_fractions_match_oracle(cuda_device, full):
+def test_partial_fractions_match_oracle(cuda_device, full, sloppy):
+    """FP64 multi-shift, and the mixed one (FP32 Krylov iteration, refinement
+    with FP32 or FP16S sloppy iterations): the same answer to 1e-8."""
     dims = (8, 8, 8, 8)
     F, L = fields(dims, cfg_id=0, eps=0.3)
     g = make_gauge(dims, F, L, full_links=full)
@@ -61,8 +64,8 @@ def test_partial_fractions_match_oracle(cuda_device, full):
     lo, hi = hisq().spectral_bounds(g, mass, 200)
     a0, al, sh, delta = hisq().zolotarev_inv_sqrt(lo, 1.05 * hi, 12)
     b = synth.gaussian_source(dims, 12, 1, parity=0)[0]
-    flush(f"rational 8^4 bounds [{lo:.3e}, {hi:.3e}] delta={delta:.2e}")
-    rc, st, got = run(g, dims, mass, a0, al, sh, b)
+    flush(f"rational 8^4 bounds [{lo:.3e}, {hi:.3e}] delta={delta:.2e} sloppy {sloppy}")
+    rc, st, got = run(g, dims, mass, a0, al, sh, b, sloppy_prec=sloppy)
     assert rc == 0, st
     assert all(s["true_residual"] <= 1e-10 for s in st)
     want = R.rational_apply(dims, F, L, mass, a0, al, sh, b, tol=1e-12)

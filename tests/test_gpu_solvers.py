@@ -163,11 +163,12 @@ def test_free_field_solve_closed_form():
     g.close()
 
 
-@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
 @pytest.mark.parametrize("nshift", [1, 4, 12])
 def test_multishift(c1, nshift, sloppy):
     """FP64 multi-shift, and the mixed form (FP32 Krylov iteration, FP64
-    reliable updates of the base, FP32-sloppy refinement of every shift)."""
+    reliable updates of the base, then every shift refined by the batched
+    mixed CG with FP32 or FP16S sloppy iterations)."""
     import torch
     dims, F, L, g = c1
     mass = 0.05
