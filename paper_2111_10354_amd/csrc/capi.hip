@@ -84,7 +84,7 @@ hisq_gauge_s::~hisq_gauge_s() {
 
 extern "C" {
 
-int hisq_version(void) { return 100; }
+int hisq_version(void) { return HISQ_VERSION; }
 
 const char *hisq_last_error(void) { return get_error(); }
 

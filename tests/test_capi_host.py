@@ -43,6 +43,12 @@ def test_binding_lists_every_export():
         assert hasattr(hisq.LIB, n)
 
 
+def test_library_version_matches_the_header(lib):
+    text = open(HEADER).read()
+    want = int(re.search(r"#define HISQ_VERSION (\d+)", text).group(1))
+    assert lib.hisq_version() == want
+
+
 def test_spinor_bytes(lib):
     f = lib.hisq_spinor_bytes
     f.restype = C.c_size_t
