@@ -240,3 +240,16 @@ def test_binding_rejects_undersized_buffers_before_any_call():
     for i, call in enumerate(calls):
         with pytest.raises(ValueError):
             call()
+
+
+def test_c_abi_check_program_builds(tmp_path):
+    """tests/capi_c_check.cpp (run on the GPU by test_gpu_capi_c.py) compiles
+    and links against the library and the C oracle from the header alone."""
+    import shutil
+    import sys
+    if shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("hipcc not available")
+    sys.path.insert(0, ROOT)
+    import __graft_entry__ as entry
+    exe = entry.build_capi_check(str(tmp_path / "capi_c_check"))
+    assert os.path.exists(exe)
