@@ -206,6 +206,9 @@ def main():
         sys.exit(2)
 
     import synth  # input generator only
+    # minutes-long solves (the 96^3x24 ones): the library prints its progress
+    # every 2000 iterations to stderr, so a long run is never silent
+    os.environ.setdefault("HISQ_SOLVER_TRACE", "1")
     tune = args.tune_cache if args.tune_cache and os.path.isdir(os.path.dirname(args.tune_cache)) else None
     dims = tuple(int(v) for v in args.dims.split(","))
     if args.c3_solvers:
@@ -219,8 +222,6 @@ def main():
         run_mrhs_only(args, dims, tune)
         return
     if args.c5_solve:
-        # minutes-long solves: the library reports progress every 2000 iterations
-        os.environ.setdefault("HISQ_SOLVER_TRACE", "1")
         fl = generate_fields(("c5",), dims)
         import torch
         from paper_2111_10354_amd import hisq
