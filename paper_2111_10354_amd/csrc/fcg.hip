@@ -348,8 +348,10 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
     HISQ_HIP_CHECK(hipMemcpyAsync(&b2, w.scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
     HISQ_HIP_CHECK(hipStreamSynchronize(s));
 
-    // HISQ_SOLVER_TRACE=1 prints one line per reliable update to stderr
+    // HISQ_SOLVER_TRACE=1 prints the reliable update at the start, after every
+    // 2000 iterations and at convergence to stderr
     static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
+    int next_report = 2000;
     FcgState hs;
     std::memset(&hs, 0, sizeof(hs));
     hs.cg.stop2 = kResidualMargin * kResidualMargin * prm.tol * prm.tol * b2;  // iterated-residual trigger (tightened below)
@@ -386,10 +388,12 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
         }
         if ((rc = fcg_true_residual(g, w, &tr, s))) return rc;
         hs.cg.reliable += 1;
-        if (trace)
+        if (trace && (first || hs.cg.iter >= next_report || tr <= hs.cg.true2)) {
             std::fprintf(stderr, "[fcg] iter %d reliable %d |r|/|b| true %.3e iterated %.3e\n", hs.cg.iter,
                          hs.cg.reliable, std::sqrt(tr / std::max(b2, 1e-300)),
                          std::sqrt(std::max(hs.rr, 0.0) / std::max(b2, 1e-300)));
+            next_report = (hs.cg.iter / 2000 + 1) * 2000;
+        }
         if (!std::isfinite(tr)) {
             fallback = broke = true;
             break;
