@@ -314,6 +314,22 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
                        hisq_solver_stats *st, void *stream);
 
 /*
+ * Multi-shift CG for several sources with the same shifts (the paper's
+ * multi-RHS and multiple-shift CG together, Sec. 2): (A + sigma_k) x_jk = b_j.
+ * With a sloppy precision other than FP64 the sources run in lockstep: their
+ * base directions form one multi-RHS stack, so every link load of the Dslash
+ * serves all of them, and the final refinement is one batched solve over all
+ * (source, shift) pairs.  With FP64 the sources are solved one after another.
+ *   b   device FP64 spinors [nsrc][3][Vh];  x device FP64 [nsrc][nshift][3][Vh]
+ *   st  host array of nsrc * nshift stats, [source][shift] (or NULL)
+ *   1 <= nsrc <= 64, 1 <= nshift <= 256, nsrc * nshift <= 1024; b and x must
+ *   not overlap.  Returns the worst status over all (source, shift) pairs.
+ */
+int hisq_multishift_cg_batched(hisq_gauge_t g, double mass, int nsrc, int nshift,
+                               const double *shifts, const double *b, double *x,
+                               const hisq_solver_params *p, hisq_solver_stats *st, void *stream);
+
+/*
  * Rational functions of A, the solver-side part of rational hybrid Monte
  * Carlo (the paper's RHMC for 2+1 flavours and its multiple-shift CG, Sec. 2;
  * most of the RHMC time goes into these CG solves, Sec. 3): with a rational
@@ -330,6 +346,19 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
 int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, const double *alpha,
                         const double *shift, const double *b, double *out,
                         const hisq_solver_params *p, hisq_solver_stats *st, void *stream);
+
+/*
+ * hisq_rational_apply for nsrc sources (several pseudofermion fields) through
+ * one hisq_multishift_cg_batched solve: out_j = alpha0 b_j + sum_k alpha[k]
+ * (A + shift[k])^(-1) b_j.
+ *   b, out  device FP64 spinors [nsrc][3][Vh], not overlapping
+ *   st      host array of nsrc * nterm stats, [source][term] (or NULL)
+ *   1 <= nsrc <= 64, nsrc * nterm <= 1024.
+ */
+int hisq_rational_apply_batched(hisq_gauge_t g, double mass, int nsrc, double alpha0, int nterm,
+                                const double *alpha, const double *shift, const double *b,
+                                double *out, const hisq_solver_params *p, hisq_solver_stats *st,
+                                void *stream);
 
 /*
  * Zolotarev's optimal rational approximation of x^(-1/2) on [lmin, lmax]

@@ -331,6 +331,28 @@ int hisq_cg_solve(hisq_gauge_t g, double mass, int nrhs, const double *b, double
     return cg_solve_fallback(g, mass, nrhs, b, x, prm, st, (hipStream_t)stream);
 }
 
+// validation shared by the single- and multi-source multi-shift entry points
+static int check_multishift(hisq_gauge_t g, double mass, int nsrc, int nshift, const double *shifts,
+                            const double *b, double *x, const hisq_solver_params &prm) {
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
+    if (prm.precond) return fail(HISQ_ERR_UNSUPPORTED, "multi-shift CG takes no preconditioner");
+    if (nsrc < 1 || nsrc > 64) return fail(HISQ_ERR_INVALID, "1 <= nsrc <= 64");
+    if (nshift < 1 || nshift > 256 || !shifts)
+        return fail(HISQ_ERR_INVALID, "1 <= nshift <= 256 and shifts are required");
+    if (nsrc * nshift > 1024) return fail(HISQ_ERR_INVALID, "nsrc * nshift must not exceed 1024");
+    for (int k = 0; k < nshift; ++k)
+        if (!std::isfinite(shifts[k]) || !(shifts[k] + 4.0 * mass * mass > 0.0))
+            return fail(HISQ_ERR_INVALID, "every shift must be finite with sigma + 4 m^2 > 0");
+    if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
+    if ((rc = check_spinors(b, x))) return rc;
+    const size_t sb = spinor_bytes(F64, g->geom.vh);
+    if (bytes_overlap(b, sb * nsrc, x, sb * (size_t)nshift * nsrc)) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
+    if (!g->links[F64][0].p) return fail(HISQ_ERR_UNSUPPORTED, "the handle lacks packed FP64 links");
+    return HISQ_OK;
+}
+
 int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *shifts, const double *b,
                        double *x, const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
     TraceRange tr_("hisq_multishift_cg");
@@ -339,20 +361,23 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
     hisq_solver_params prm;
     if (p) prm = *p;
     else hisq_solver_params_default(&prm);
-    if ((rc = check_params(prm))) return rc;
-    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
-    if (prm.precond) return fail(HISQ_ERR_UNSUPPORTED, "multi-shift CG takes no preconditioner");
-    if (nshift < 1 || nshift > 256 || !shifts)
-        return fail(HISQ_ERR_INVALID, "1 <= nshift <= 256 and shifts are required");
-    for (int k = 0; k < nshift; ++k)
-        if (!std::isfinite(shifts[k]) || !(shifts[k] + 4.0 * mass * mass > 0.0))
-            return fail(HISQ_ERR_INVALID, "every shift must be finite with sigma + 4 m^2 > 0");
-    if (!b || !x) return fail(HISQ_ERR_INVALID, "b and x are required");
-    if ((rc = check_spinors(b, x))) return rc;
-    const size_t sb = spinor_bytes(F64, g->geom.vh);
-    if (bytes_overlap(b, sb, x, sb * (size_t)nshift)) return fail(HISQ_ERR_INVALID, "b and x must not overlap");
+    if ((rc = check_multishift(g, mass, 1, nshift, shifts, b, x, prm))) return rc;
     std::lock_guard<std::mutex> lk(g->mu);
     return multishift_solve(g, mass, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
+}
+
+int hisq_multishift_cg_batched(hisq_gauge_t g, double mass, int nsrc, int nshift, const double *shifts,
+                               const double *b, double *x, const hisq_solver_params *p, hisq_solver_stats *st,
+                               void *stream) {
+    TraceRange tr_("hisq_multishift_cg_batched");
+    int rc = check_handle(g);
+    if (rc) return rc;
+    hisq_solver_params prm;
+    if (p) prm = *p;
+    else hisq_solver_params_default(&prm);
+    if ((rc = check_multishift(g, mass, nsrc, nshift, shifts, b, x, prm))) return rc;
+    std::lock_guard<std::mutex> lk(g->mu);
+    return multishift_solve_batched(g, mass, nsrc, nshift, shifts, b, x, prm, st, (hipStream_t)stream);
 }
 
 // The coefficient outputs of the rational-approximation routines are written
@@ -409,10 +434,9 @@ int hisq_rational_remez(double power, double lmin, double lmax, int npole, doubl
     return remez_power(power, lmin, lmax, npole, alpha0, alpha, shift, delta);
 }
 
-int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, const double *alpha,
-                        const double *shift, const double *b, double *out, const hisq_solver_params *p,
-                        hisq_solver_stats *st, void *stream) {
-    TraceRange tr_("hisq_rational_apply");
+static int rational_apply_checked(hisq_gauge_t g, double mass, int nsrc, double alpha0, int nterm,
+                                  const double *alpha, const double *shift, const double *b, double *out,
+                                  const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
     int rc = check_handle(g);
     if (rc) return rc;
     hisq_solver_params prm;
@@ -421,7 +445,9 @@ int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, c
     if ((rc = check_params(prm))) return rc;
     if (!(mass > 0.0) || !std::isfinite(mass)) return fail(HISQ_ERR_INVALID, "mass must be positive");
     if (prm.precond) return fail(HISQ_ERR_UNSUPPORTED, "rational apply takes no preconditioner");
+    if (nsrc < 1 || nsrc > 64) return fail(HISQ_ERR_INVALID, "1 <= nsrc <= 64");
     if (nterm < 0 || nterm > 256) return fail(HISQ_ERR_INVALID, "0 <= nterm <= 256");
+    if (nsrc * nterm > 1024) return fail(HISQ_ERR_INVALID, "nsrc * nterm must not exceed 1024");
     if (nterm > 0 && (!alpha || !shift)) return fail(HISQ_ERR_INVALID, "alpha and shift are required");
     if (!std::isfinite(alpha0)) return fail(HISQ_ERR_INVALID, "alpha0 must be finite");
     for (int k = 0; k < nterm; ++k)
@@ -429,11 +455,25 @@ int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, c
             return fail(HISQ_ERR_INVALID, "every alpha and shift must be finite with shift + 4 m^2 > 0");
     if (!b || !out) return fail(HISQ_ERR_INVALID, "b and out are required");
     if ((rc = check_spinors(b, out))) return rc;
-    const size_t sb = spinor_bytes(F64, g->geom.vh);
+    const size_t sb = spinor_bytes(F64, g->geom.vh) * nsrc;
     if (bytes_overlap(b, sb, out, sb)) return fail(HISQ_ERR_INVALID, "b and out must not overlap");
     if (!g->links[F64][0].p) return fail(HISQ_ERR_UNSUPPORTED, "the handle lacks packed FP64 links");
     std::lock_guard<std::mutex> lk(g->mu);
-    return rational_apply(g, mass, alpha0, nterm, alpha, shift, b, out, prm, st, (hipStream_t)stream);
+    return rational_apply(g, mass, nsrc, alpha0, nterm, alpha, shift, b, out, prm, st, (hipStream_t)stream);
+}
+
+int hisq_rational_apply(hisq_gauge_t g, double mass, double alpha0, int nterm, const double *alpha,
+                        const double *shift, const double *b, double *out, const hisq_solver_params *p,
+                        hisq_solver_stats *st, void *stream) {
+    TraceRange tr_("hisq_rational_apply");
+    return rational_apply_checked(g, mass, 1, alpha0, nterm, alpha, shift, b, out, p, st, stream);
+}
+
+int hisq_rational_apply_batched(hisq_gauge_t g, double mass, int nsrc, double alpha0, int nterm,
+                                const double *alpha, const double *shift, const double *b, double *out,
+                                const hisq_solver_params *p, hisq_solver_stats *st, void *stream) {
+    TraceRange tr_("hisq_rational_apply_batched");
+    return rational_apply_checked(g, mass, nsrc, alpha0, nterm, alpha, shift, b, out, p, st, stream);
 }
 
 int hisq_spectral_bounds(hisq_gauge_t g, double mass, int iters, double *lmin, double *lmax, void *stream) {

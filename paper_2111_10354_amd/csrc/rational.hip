@@ -536,21 +536,25 @@ __global__ __launch_bounds__(256) void k_scale_into(int vh, const d2v *__restric
 }
 
 // ------------------------------------------------------------------ host drivers
-int rational_apply(hisq_gauge_s *g, double mass, double alpha0, int n, const double *alpha, const double *shift,
-                   const double *b, double *out, const hisq_solver_params &prm, hisq_solver_stats *st,
-                   hipStream_t s) {
+// nsrc sources (stacks of FP64 spinors): one multi-shift solve for all of
+// them (in lockstep in mixed precision), then the combination per source
+int rational_apply(hisq_gauge_s *g, double mass, int nsrc, double alpha0, int n, const double *alpha,
+                   const double *shift, const double *b, double *out, const hisq_solver_params &prm,
+                   hisq_solver_stats *st, hipStream_t s) {
     const int vh = g->geom.vh;
     const size_t s64 = spinor_bytes(F64, vh);
     DevBuf xs, al;
     int rc, worst = HISQ_OK;
     if (n > 0) {
-        if ((rc = xs.alloc(s64 * n)) || (rc = al.alloc(sizeof(double) * n))) return rc;
-        worst = multishift_solve(g, mass, n, shift, b, (double *)xs.p, prm, st, s);
+        if ((rc = xs.alloc(s64 * n * (size_t)nsrc)) || (rc = al.alloc(sizeof(double) * n))) return rc;
+        worst = multishift_solve_batched(g, mass, nsrc, n, shift, b, (double *)xs.p, prm, st, s);
         if (worst < 0) return worst;
         HISQ_HIP_CHECK(hipMemcpyAsync(al.p, alpha, sizeof(double) * n, hipMemcpyHostToDevice, s));
     }
-    hipLaunchKernelGGL(k_rational_combine, dim3((vh + 255) / 256), dim3(256), 0, s, vh, (const d2v *)b, alpha0, n,
-                       (const double *)al.p, (const d2v *)xs.p, (d2v *)out);
+    for (int j = 0; j < nsrc; ++j)
+        hipLaunchKernelGGL(k_rational_combine, dim3((vh + 255) / 256), dim3(256), 0, s, vh,
+                           (const d2v *)((const char *)b + s64 * j), alpha0, n, (const double *)al.p,
+                           (const d2v *)((const char *)xs.p + s64 * (size_t)n * j), (d2v *)((char *)out + s64 * j));
     HISQ_HIP_CHECK(hipGetLastError());
     HISQ_HIP_CHECK(hipStreamSynchronize(s));
     return worst;

@@ -207,6 +207,10 @@ int fcg_solve(hisq_gauge_s *g, double mass, const double *b, double *x, const hi
 
 int multishift_solve(hisq_gauge_s *g, double mass, int nshift, const double *shifts, const double *b,
                      double *x, const hisq_solver_params &p, hisq_solver_stats *st, hipStream_t s);
+// nsrc sources b [nsrc][spinor], x [nsrc][nshift][spinor], st [nsrc][nshift]
+int multishift_solve_batched(hisq_gauge_s *g, double mass, int nsrc, int nshift, const double *shifts,
+                             const double *b, double *x, const hisq_solver_params &p, hisq_solver_stats *st,
+                             hipStream_t s);
 
 // Zolotarev's minimax relative approximation of x^(-1/2) on [lmin, lmax] in
 // partial fractions alpha0 + sum_k alpha[k] / (x + shift[k]); delta = its
@@ -216,9 +220,9 @@ int zolotarev_inv_sqrt(double lmin, double lmax, int n, double *alpha0, double *
 int remez_power(double power, double lmin, double lmax, int n, double *alpha0, double *alpha, double *shift,
                 double *delta);
 // out = alpha0 b + sum_k alpha[k] (A + shift[k])^(-1) b by one multi-shift CG.
-int rational_apply(hisq_gauge_s *g, double mass, double alpha0, int n, const double *alpha, const double *shift,
-                   const double *b, double *out, const hisq_solver_params &prm, hisq_solver_stats *st,
-                   hipStream_t s);
+int rational_apply(hisq_gauge_s *g, double mass, int nsrc, double alpha0, int n, const double *alpha,
+                   const double *shift, const double *b, double *out, const hisq_solver_params &prm,
+                   hisq_solver_stats *st, hipStream_t s);
 // HISQ smearing of canonical thin links into folded fat and Naik links (FP64).
 int smear_links(const int dims[4], const double *thin, double *fat, double *lng, unsigned flags, hipStream_t s);
 

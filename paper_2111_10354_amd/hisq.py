@@ -67,6 +67,8 @@ def _load():
                                     C.POINTER(SolverStats), vp]),
         "hisq_multishift_cg": (C.c_int, [vp, C.c_double, C.c_int, dp, vp, vp, C.POINTER(SolverParams),
                                          C.POINTER(SolverStats), vp]),
+        "hisq_multishift_cg_batched": (C.c_int, [vp, C.c_double, C.c_int, C.c_int, dp, vp, vp,
+                                                 C.POINTER(SolverParams), C.POINTER(SolverStats), vp]),
         "hisq_precond_apply": (C.c_int, [vp, vp, vp, vp, vp]),
         "hisq_autotune": (C.c_int, [vp, C.c_int, C.c_int, C.c_char_p, vp]),
         "hisq_gauge_set_thin": (C.c_int, [vp, vp, vp]),
@@ -81,6 +83,8 @@ def _load():
         "hisq_gauge_links_compressed": (C.c_int, [vp]),
         "hisq_rational_apply": (C.c_int, [vp, C.c_double, C.c_double, C.c_int, dp, dp, vp, vp,
                                           C.POINTER(SolverParams), C.POINTER(SolverStats), vp]),
+        "hisq_rational_apply_batched": (C.c_int, [vp, C.c_double, C.c_int, C.c_double, C.c_int, dp, dp, vp, vp,
+                                                  C.POINTER(SolverParams), C.POINTER(SolverStats), vp]),
         "hisq_zolotarev_inv_sqrt": (C.c_int, [C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
         "hisq_rational_remez": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp, dp]),
         "hisq_spectral_bounds": (C.c_int, [vp, C.c_double, C.c_int, dp, dp, vp]),
@@ -103,7 +107,8 @@ EXPORTS = ("hisq_version", "hisq_last_error", "hisq_spinor_bytes", "hisq_gauge_c
            "hisq_nn_num_weights", "hisq_nn_get_weights", "hisq_nn_set_weights", "hisq_nn_loss_grad",
            "hisq_nn_train_step", "hisq_gauge_links_compressed", "hisq_rational_apply",
            "hisq_zolotarev_inv_sqrt", "hisq_rational_remez", "hisq_spectral_bounds",
-           "hisq_dslash_multi_rhs_noalloc", "hisq_smear_links")
+           "hisq_dslash_multi_rhs_noalloc", "hisq_smear_links", "hisq_multishift_cg_batched",
+           "hisq_rational_apply_batched")
 
 LINKS_FULL = 1 << 8  # hisq_gauge_create: store every link whole
 
@@ -287,6 +292,41 @@ def multishift_cg(g: Gauge, mass: float, shifts, b, x, params: SolverParams | No
                                 C.byref(params) if params is not None else None, st, _stream(stream))
     _check(rc, allow_soft=True)
     return rc, [s.as_dict() for s in st]
+
+
+def multishift_cg_batched(g: Gauge, mass: float, nsrc: int, shifts, b, x, params: SolverParams | None = None,
+                          stream=None):
+    """nsrc sources b [nsrc][spinor] with the same shifts; x [nsrc][nshift][spinor].
+    Returns (status, [stats per (source, shift)], source-major)."""
+    n, m = len(shifts), int(nsrc)
+    sb = spinor_bytes("fp64", g.vh)
+    _need(b, sb * m, "b")
+    _need(x, sb * n * m, "x")
+    sh = (C.c_double * n)(*[float(v) for v in shifts])
+    st = (SolverStats * (n * m))()
+    rc = LIB.hisq_multishift_cg_batched(g.handle, float(mass), m, n, sh, _ptr(b), _ptr(x),
+                                        C.byref(params) if params is not None else None, st, _stream(stream))
+    _check(rc, allow_soft=True)
+    return rc, [s.as_dict() for s in st]
+
+
+def rational_apply_batched(g: Gauge, mass: float, nsrc: int, alpha0: float, alphas, shifts, b, out,
+                           params: SolverParams | None = None, stream=None):
+    """out_j = alpha0 b_j + sum_k alphas[k] (A + shifts[k])^-1 b_j for nsrc sources
+    (stacks [nsrc][spinor]); returns (status, [stats per (source, term)])."""
+    n, m = len(shifts), int(nsrc)
+    if len(alphas) != n:
+        raise ValueError("alphas and shifts differ in length")
+    sb = spinor_bytes("fp64", g.vh)
+    _need(b, sb * m, "b")
+    _need(out, sb * m, "out")
+    al = (C.c_double * max(n, 1))(*[float(v) for v in alphas])
+    sh = (C.c_double * max(n, 1))(*[float(v) for v in shifts])
+    st = (SolverStats * max(n * m, 1))()
+    rc = LIB.hisq_rational_apply_batched(g.handle, float(mass), m, float(alpha0), n, al, sh, _ptr(b), _ptr(out),
+                                         C.byref(params) if params is not None else None, st, _stream(stream))
+    _check(rc, allow_soft=True)
+    return rc, [s.as_dict() for s in st[:n * m]]
 
 
 def rational_apply(g: Gauge, mass: float, alpha0: float, alphas, shifts, b, out,

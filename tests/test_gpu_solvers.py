@@ -253,3 +253,95 @@ def test_batched_solve_compacts_finished_rhs(c1, sloppy, graph_chunk):
     early = max(st[i]["iterations"] for i in (0, 2, 3))
     late = min(st[i]["iterations"] for i in (1, 4))
     assert 2 * early < late, st
+
+
+def _ms_batched(g, dims, mass, srcs, shifts, **kw):
+    import torch
+    vh = synth.volume(dims) // 2
+    m, n = len(srcs), len(shifts)
+    bd = to_device(np.concatenate([encode(to_cb(dims, s, 0), "fp64") for s in srcs]))
+    x = torch.full((m * n * 48 * vh,), 0x55, dtype=torch.uint8, device="cuda")
+    rc, st = hisq().multishift_cg_batched(g, mass, m, list(shifts), bd, x, hisq().solver_params(**kw))
+    xs = to_host(x).reshape(m, n, -1)
+    sol = [[from_cb(dims, decode(xs[j, k], vh, "fp64"), 0) for k in range(n)] for j in range(m)]
+    return rc, st, sol
+
+
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
+def test_multishift_batched(c1, sloppy):
+    """Three sources sharing four (unsorted) shifts in one call; the mixed
+    form iterates them in lockstep through the three-RHS Dslash.  Every
+    (source, shift) solution meets the tolerance on the oracle's operator, in
+    the caller's [source][shift] order, with its own stats.  The sources
+    differ in norm by 1e3, so a stopping rule shared between them would leave
+    the small one short."""
+    dims, F, L, g = c1
+    mass = 0.05
+    shifts = [0.3, 0.0, 0.01, 0.08]
+    srcs = synth.gaussian_source(dims, 4, 3, parity=0, index0=80)
+    srcs[1] = 1e-3 * srcs[1]
+    flush(f"batched multishift 8^4 3 sources x 4 shifts {sloppy}")
+    rc, st, sol = _ms_batched(g, dims, mass, srcs, shifts, sloppy_prec=sloppy)
+    assert rc == 0, st
+    assert len(st) == 12
+    for j in range(3):
+        for k, s in enumerate(shifts):
+            res = oracle.true_residual(dims, F, L, mass, srcs[j], sol[j][k], sigma=s)
+            assert res <= TOL * RES_SLACK, (j, k, res)
+            assert st[j * 4 + k]["true_residual"] <= TOL, (j, k)
+            assert st[j * 4 + k]["iterations"] > 0
+
+
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+def test_multishift_batched_one_source_is_single(c1, sloppy):
+    """nsrc = 1 runs exactly the single-source solver: bitwise the same x."""
+    import torch
+    dims, F, L, g = c1
+    mass = 0.05
+    shifts = [0.0, 0.02, 0.2]
+    b = synth.gaussian_source(dims, 4, 1, parity=0, index0=90)[0]
+    rc, st, sol = _ms_batched(g, dims, mass, [b], shifts, sloppy_prec=sloppy)
+    assert rc == 0
+    vh = synth.volume(dims) // 2
+    bd = to_device(encode(to_cb(dims, b, 0), "fp64"))
+    x = torch.zeros(len(shifts) * 48 * vh, dtype=torch.uint8, device="cuda")
+    rc1, _ = hisq().multishift_cg(g, mass, shifts, bd, x, hisq().solver_params(sloppy_prec=sloppy))
+    assert rc1 == 0
+    xs = to_host(x).reshape(len(shifts), -1)
+    for k in range(len(shifts)):
+        assert np.array_equal(from_cb(dims, decode(xs[k], vh, "fp64"), 0), sol[0][k]), k
+
+
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+def test_multishift_batched_zero_source(c1, sloppy):
+    """A zero source among others: its solutions are exactly zero and the
+    others still converge."""
+    dims, F, L, g = c1
+    mass = 0.05
+    shifts = [0.0, 0.1]
+    srcs = synth.gaussian_source(dims, 4, 2, parity=0, index0=95)
+    srcs = [srcs[0], np.zeros_like(srcs[0]), srcs[1]]
+    rc, st, sol = _ms_batched(g, dims, mass, srcs, shifts, sloppy_prec=sloppy)
+    assert rc == 0, st
+    for k in range(2):
+        assert not np.any(sol[1][k])
+        for j in (0, 2):
+            assert oracle.true_residual(dims, F, L, mass, srcs[j], sol[j][k], sigma=shifts[k]) <= TOL * RES_SLACK
+
+
+def test_multishift_batched_invalid(c1):
+    import torch
+    dims, F, L, g = c1
+    vh = synth.volume(dims) // 2
+    sb = 48 * vh
+    b = torch.zeros(65 * sb, dtype=torch.uint8, device="cuda")
+    x = torch.zeros(65 * 17 * sb, dtype=torch.uint8, device="cuda")
+    H = hisq()
+    for nsrc, shifts in ((0, [0.0]), (65, [0.0]), (64, [0.01 * i for i in range(17)]), (2, [0.0, -0.05])):
+        with pytest.raises(H.HisqError) as e:
+            H.multishift_cg_batched(g, 0.1, nsrc, shifts, b, x)
+        assert e.value.code == H.ERR_INVALID, (nsrc, len(shifts))
+    # solutions overlapping the sources
+    with pytest.raises(H.HisqError) as e:
+        H.multishift_cg_batched(g, 0.1, 2, [0.0, 0.1], x[sb:], x)
+    assert e.value.code == H.ERR_INVALID
