@@ -6,7 +6,8 @@
 //  * hisq_dslash_multi_rhs with the (A + sigma_i) epilogue (FP64, 3 RHS)
 //    against oracle_normal_op;
 //  * hisq_cg_solve (plain FP64 and mixed FP32, 2 RHS) and hisq_multishift_cg
-//    (FP64 and mixed, 3 shifts) on the oracle's true residual;
+//    (FP64 and mixed, 3 shifts) on the oracle's true residual, and
+//    hisq_multishift_cg_batched (mixed, 2 sources x 2 shifts);
 //  * that bad arguments return HISQ_ERR_INVALID with a message.
 // Prints one line per check and exits non-zero on the first failure.
 #include <hip/hip_runtime_api.h>
@@ -222,6 +223,42 @@ int main() {
             std::printf("multishift sloppy %d shift %g: oracle true residual %.2e\n", sloppy, shifts[k], res);
             CHECK(res <= 1e-10, "multishift sloppy %d shift %d: %.3e", sloppy, k, res);
         }
+    }
+
+    // two sources with the same shifts in one call (mixed: lockstep through the 2-RHS Dslash)
+    {
+        const int ns = 2, m = 2;
+        const double shifts[ns] = {0.05, 0.0};
+        std::vector<std::vector<double>> bs;
+        std::vector<double> stack;
+        for (int j = 0; j < m; ++j) {
+            bs.push_back(random_field(0));
+            const std::vector<double> bp = to_parity(bs[j], 0);
+            stack.insert(stack.end(), bp.begin(), bp.end());
+        }
+        Dev db(m * sb), dx(m * ns * sb);
+        HIP(hipMemcpy(db.p, stack.data(), m * sb, hipMemcpyHostToDevice));
+        hisq_solver_params prm;
+        hisq_solver_params_default(&prm);
+        prm.sloppy_prec = HISQ_PREC_FP32;
+        hisq_solver_stats st[m * ns];
+        rc = hisq_multishift_cg_batched(g, mass, m, ns, shifts, (const double *)db.p, (double *)dx.p, &prm, st,
+                                        nullptr);
+        CHECK(rc == HISQ_OK, "batched multishift: %d %s", rc, hisq_last_error());
+        std::vector<double> xs(m * ns * 6 * VH);
+        HIP(hipMemcpy(xs.data(), dx.p, m * ns * sb, hipMemcpyDeviceToHost));
+        for (int j = 0; j < m; ++j)
+            for (int k = 0; k < ns; ++k) {
+                const size_t at = (size_t)(j * ns + k) * 6 * VH;
+                std::vector<double> xk(xs.begin() + at, xs.begin() + at + 6 * VH);
+                const double res = oracle_true_residual(L, fat.data(), lng.data(), mass, shifts[k], bs[j].data(),
+                                                        from_parity(xk, 0).data());
+                std::printf("batched multishift source %d shift %g: oracle true residual %.2e\n", j, shifts[k], res);
+                CHECK(res <= 1e-10 && st[j * ns + k].status == HISQ_OK, "batched multishift %d %d: %.3e", j, k, res);
+            }
+        rc = hisq_multishift_cg_batched(g, mass, 0, ns, shifts, (const double *)db.p, (double *)dx.p, &prm, st,
+                                        nullptr);
+        CHECK(rc == HISQ_ERR_INVALID, "nsrc 0: %d", rc);
     }
 
     // error paths
