@@ -163,4 +163,9 @@ def test_batched_sources_match_oracle(cuda_device, sloppy):
         phi = from_cb(dims, decode(got[j], vh, "fp64"), 0)
         want = R.rational_apply(dims, F, L, mass, a0, al, sh, etas[j], tol=1e-12)
         assert np.linalg.norm(phi - want) / np.linalg.norm(want) < 1e-8, j
+    # no poles: out_j = alpha0 b_j exactly, for every source
+    out.fill_(0x77)
+    rc, st = hisq().rational_apply_batched(g, mass, 4, 2.5, [], [], bd, out)
+    assert rc == 0 and st == []
+    assert np.array_equal(to_host(out).view(np.float64), 2.5 * to_host(bd).view(np.float64))
     g.close()

@@ -345,3 +345,23 @@ def test_multishift_batched_invalid(c1):
     with pytest.raises(H.HisqError) as e:
         H.multishift_cg_batched(g, 0.1, 2, [0.0, 0.1], x[sb:], x)
     assert e.value.code == H.ERR_INVALID
+
+
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+def test_multishift_batched_maximum_size(cuda_device, sloppy):
+    """The largest accepted batch, 64 sources x 16 shifts = 1024 systems (on
+    4^4): every solution meets the tolerance on the oracle's operator."""
+    dims = (4, 4, 4, 4)
+    F, L = fields(dims, cfg_id=2, eps=0.3)
+    g = make_gauge(dims, F, L)
+    mass = 0.05
+    shifts = [float(v) for v in np.geomspace(1e-4, 3.0, 16)]
+    srcs = synth.gaussian_source(dims, 6, 64, parity=0)
+    flush(f"batched multishift 4^4 64 sources x 16 shifts {sloppy}")
+    rc, st, sol = _ms_batched(g, dims, mass, list(srcs), shifts, sloppy_prec=sloppy)
+    assert rc == 0, [s for s in st if s["status"]][:3]
+    assert len(st) == 1024 and all(s["true_residual"] <= TOL for s in st)
+    worst = max(oracle.true_residual(dims, F, L, mass, srcs[j], sol[j][k], sigma=s)
+                for j in range(64) for k, s in enumerate(shifts))
+    assert worst <= TOL * RES_SLACK, worst
+    g.close()
