@@ -177,6 +177,8 @@ def main():
                     help="autotuner cache (JSON lines); shapes found there are used without timing")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 48^3x12 multi-RHS sweep")
     ap.add_argument("--no-c3", action="store_true", help="skip the 48^3x12 batched and multi-shift solves")
+    ap.add_argument("--c2-dslash", action="store_true",
+                    help="only the 32^3x8 single-RHS Dslash in FP64, FP32 and FP16S (for counter runs)")
     ap.add_argument("--c3-solvers", action="store_true",
                     help="only the 48^3x12 solves (plain, mixed, 16-RHS batched, 12-shift, A^(-1/2))")
     ap.add_argument("--fields-cache", type=str, default=None,
@@ -217,6 +219,12 @@ def main():
         from paper_2111_10354_amd import hisq
         out, _ = run_c3_solvers(hisq, torch, tune, fl["c3"])
         print(json.dumps(out), flush=True)
+        return
+    if args.c2_dslash:
+        fl = generate_fields(("c2",), dims)
+        import torch
+        from paper_2111_10354_amd import hisq
+        print(json.dumps(run_c2_dslash(hisq, torch, tune, fl["c2"], args.steps, min(args.warmup, 50))), flush=True)
         return
     if args.mrhs:
         run_mrhs_only(args, dims, tune)
@@ -362,10 +370,11 @@ def main():
     if full and not args.no_sweep:
         sweep = run_mrhs_sweep(hisq, torch, tune, fields["c3"])
 
-    # ---- CG time to solution on the 32^3 x 8 workload
+    # ---- CG time to solution on the 32^3 x 8 workload, and its Dslash per precision
     cg = None
     if full and not args.no_cg:
         cg, solutions["c2"] = run_cg(hisq, torch, fields["c2"])
+        cg["dslash_single_rhs"] = run_c2_dslash(hisq, torch, tune, fields["c2"], 200, 50)
 
     # ---- batched and multi-shift solves on the 48^3 x 12 workload
     c3 = None
@@ -546,6 +555,46 @@ def run_cg(hisq, torch, fields):
     out["speedup_chosen_vs_plain"] = round(out["plain_fp64"]["seconds"] / out[best]["seconds"], 3)
     g.close()
     return out, (dims, mass, items)
+
+
+def link_bytes_per_site(prec, comp):
+    """Algorithmic link bytes of one output site: 16 links, the long ones as
+    two rows plus a sign word (comp 1) or a complex factor (comp 2)."""
+    real = {"fp64": 8, "fp32": 4, "fp16s": 2}[prec]
+    if prec == "fp64" or not comp:
+        return real * 16 * 18
+    return real * (8 * 18 + 8 * 12) + (4 if comp == 1 else real * 16)
+
+
+def run_c2_dslash(hisq, torch, tune, fields, steps, warmup):
+    """Single-RHS single-parity Dslash on 32^3 x 8 in FP64, FP32 and FP16S
+    (long links compressed as the solvers use them; FP64 links whole), timed
+    with HIP events.  The FP32 links (120 MiB) fit in the 256 MB Infinity
+    Cache, so back-to-back launches can read them from there: the counter
+    summary in profiles/ gives the bytes that left the L2s."""
+    import synth
+    c = synth.CONFIGS["c2"]
+    dims = c["dims"]
+    vh = synth.volume(dims) // 2
+    F, L = fields
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32", "fp16s"))
+    chi = synth.gaussian_source(dims, synth.CFG_IDS["c2"], 1, parity=1)[0]
+    ccb, _ = cb_gather(dims, chi, 1)
+    res = {"workload": f"{'x'.join(map(str, dims))} single-parity Dslash, 1 RHS",
+           "long_links": ["whole", "sign", "kappa"][g.comp_mode]}
+    for p in ("fp64", "fp32", "fp16s"):
+        hisq.autotune(g, p, 1, tune)
+        i1 = torch.from_numpy(encode(ccb, p)).cuda()
+        o1 = torch.empty(hisq.spinor_bytes(p, vh), dtype=torch.uint8, device="cuda")
+        ms = time_launches(lambda: hisq.dslash_eo(g, 0, p, i1, o1), steps, warmup)
+        spin = hisq.spinor_bytes(p, vh) // vh
+        gbs = vh * (link_bytes_per_site(p, g.comp_mode) + 2 * spin) / (ms * 1e-3) / 1e9
+        res[p] = {"ms": round(ms, 5), "gbs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                  "shape": list(hisq.dslash_shape(g, p, 1, 0))}
+        log(f"C2 {p} Dslash: {ms:.4f} ms, {gbs:.0f} GB/s algorithmic, shape {res[p]['shape']}")
+        del i1, o1
+    g.close()
+    return res
 
 
 def run_mrhs_only(args, dims, tune):
