@@ -179,9 +179,11 @@ struct MsWorkspace {
 // after such an update the recurrences continue from the recomputed residual,
 // with each shifted residual taken as zeta_k times it.  The shifted residuals
 // are collinear with the base residual only up to the rounding of the FP32
-// operator, so the shifted solutions stall at a relative residual of order
-// 1e-6; the batched mixed-precision CG warm-started from them finishes every
-// (source, shift) on its own FP64 true residual.
+// operator, so the shifted solutions stall far above the target (the smaller
+// the shift, the higher: between ~1e-3 and ~1e-7 relative for shifts from
+// 1e-4 to 10 in a model of this iteration); the batched mixed-precision CG
+// warm-started from them finishes every (source, shift) on its own FP64 true
+// residual.
 //   b: nsrc FP64 sources [nsrc][spinor];  x: [nsrc][ns][spinor] in the
 //   caller's shift order;  stats: [nsrc][ns] or NULL.
 static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, const int *order,
@@ -542,7 +544,6 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     rp.sloppy_prec = HISQ_PREC_FP64;
     rp.warm_start = 1;
     std::vector<hisq_solver_stats> rs(ns);
-    const double ms_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     int worst = cg_solve(g, mass, ns, (const double *)w.bstack.p, (double *)xs.p, sig.data(), rp, rs.data(), s);
     if (worst < 0) return worst;
     // scatter back to the caller's order
@@ -564,7 +565,6 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
             stats[order[k]] = o;
         }
     }
-    (void)ms_ms;
     return worst;
 }
 
