@@ -737,6 +737,7 @@ def run_c3_solvers(hisq, torch, tune, fields):
     t_remez = time.time() - t1
     a0, al, sh, delta = hisq.zolotarev_inv_sqrt(lo, 1.05 * hi, npole)
     eta2 = float(torch.dot(b0.view(torch.float64), b0.view(torch.float64)))
+    phi_one = {}
     for sl in ("fp64", "fp32"):
         sfx = "" if sl == "fp64" else "_mixed_fp32"
         prm = hisq.solver_params(sloppy_prec=sl)
@@ -750,6 +751,7 @@ def run_c3_solvers(hisq, torch, tune, fields):
             "true_residual_max": max(v["true_residual"] for v in st)}
         log(f"C3 heat bath A^(1/4) eta ({sl} multi-shift), {npole} Remez poles (rel. error {hdelta:.1e}, "
             f"coefficients {t_remez:.3f} s): {wall:.3f} s, base {st[0]['iterations']} it")
+        phi_one[sl] = phi
         y = torch.empty_like(b0)
         (rc, st), wall = timed(lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, y, prm),
                                lambda: hisq.rational_apply(g, mass, a0, al, sh, phi, torch.empty_like(b0), warm))
@@ -762,28 +764,32 @@ def run_c3_solvers(hisq, torch, tune, fields):
         log(f"C3 action phi^+ A^(-1/2) phi ({sl} multi-shift), {npole} Zolotarev poles on [{lo:.2e}, "
             f"{1.05 * hi:.3f}] (rel. error {delta:.1e}): {wall:.3f} s, base {st[0]['iterations']} it; "
             f"S/|eta|^2 - 1 = {action / eta2 - 1:.1e}; bounds {t_bounds:.3f} s")
-    # four pseudofermion heat baths in one batched call: the mixed multi-shift
-    # iterates the sources in lockstep through the 4-RHS Dslash and refines
-    # all 4 x 16 (source, pole) systems in one batched CG
+    # four pseudofermion heat baths in one batched call: the multi-shift
+    # iterates the sources in lockstep through the 4-RHS Dslash (FP64, or FP32
+    # in the mixed form) and verifies / refines all 4 x 16 (source, pole)
+    # systems in one batched CG
     nps = 4
     bq = b[:nps * sb]
-    phis = torch.empty_like(bq)
-    prm = hisq.solver_params(sloppy_prec="fp32")
-    (rc, st), wall = timed(
-        lambda: hisq.rational_apply_batched(g, mass, nps, h0, hal, hsh, bq, phis, prm),
-        lambda: hisq.rational_apply_batched(g, mass, nps, h0, hal, hsh, bq, torch.empty_like(bq),
-                                            hisq.solver_params(sloppy_prec="fp32", max_iter=50)))
-    single = out[f"heatbath_quarter_root_remez_{npole}poles_mixed_fp32"]["seconds"]
-    d0 = (phis[:sb].view(torch.float64) - phi.view(torch.float64)).norm() / phi.view(torch.float64).norm()
-    out[f"heatbath_quarter_root_remez_{npole}poles_mixed_fp32_{nps}sources_batched"] = {
-        "status": rc, "seconds": round(wall, 4), "seconds_per_source": round(wall / nps, 4),
-        "speedup_per_source_vs_one_source": round(single / (wall / nps), 3),
-        "iterations_base_max": max(st[j * npole]["iterations"] for j in range(nps)),
-        "true_residual_max": max(v["true_residual"] for v in st),
-        "source0_rel_diff_vs_one_source_call": float(d0)}
-    log(f"C3 heat bath A^(1/4) eta for {nps} sources batched (mixed multi-shift): {wall:.3f} s, "
-        f"{wall / nps:.3f} s per source ({single / (wall / nps):.2f}x one source at a time); "
-        f"source 0 differs from the one-source call by {float(d0):.1e}")
+    for sl in ("fp64", "fp32"):
+        sfx = "" if sl == "fp64" else "_mixed_fp32"
+        phis = torch.empty_like(bq)
+        prm = hisq.solver_params(sloppy_prec=sl)
+        (rc, st), wall = timed(
+            lambda: hisq.rational_apply_batched(g, mass, nps, h0, hal, hsh, bq, phis, prm),
+            lambda: hisq.rational_apply_batched(g, mass, nps, h0, hal, hsh, bq, torch.empty_like(bq),
+                                                hisq.solver_params(sloppy_prec=sl, max_iter=50)))
+        single = out[f"heatbath_quarter_root_remez_{npole}poles{sfx}"]["seconds"]
+        ref = phi_one[sl].view(torch.float64)
+        d0 = float((phis[:sb].view(torch.float64) - ref).norm() / ref.norm())
+        out[f"heatbath_quarter_root_remez_{npole}poles{sfx}_{nps}sources_batched"] = {
+            "status": rc, "seconds": round(wall, 4), "seconds_per_source": round(wall / nps, 4),
+            "speedup_per_source_vs_one_source": round(single / (wall / nps), 3),
+            "iterations_base_max": max(st[j * npole]["iterations"] for j in range(nps)),
+            "true_residual_max": max(v["true_residual"] for v in st),
+            "source0_rel_diff_vs_one_source_call": d0}
+        log(f"C3 heat bath A^(1/4) eta for {nps} sources batched ({sl} multi-shift): {wall:.3f} s, "
+            f"{wall / nps:.3f} s per source ({single / (wall / nps):.2f}x one source at a time); "
+            f"source 0 differs from the one-source call by {d0:.1e}")
     p1 = out["plain_fp64_1rhs"]["seconds"]
     out["speedup_batched_per_rhs_vs_plain"] = round(p1 / out[f"batched_mixed_fp32_{n}rhs"]["seconds_per_rhs"], 3)
     ms = min((out[f"multishift_{sl}_{ns}shifts"] for sl in ("fp64", "fp32")), key=lambda v: v["seconds"])

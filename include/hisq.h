@@ -316,10 +316,11 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
 /*
  * Multi-shift CG for several sources with the same shifts (the paper's
  * multi-RHS and multiple-shift CG together, Sec. 2): (A + sigma_k) x_jk = b_j.
- * With a sloppy precision other than FP64 the sources run in lockstep: their
- * base directions form one multi-RHS stack, so every link load of the Dslash
- * serves all of them, and the final refinement is one batched solve over all
- * (source, shift) pairs.  With FP64 the sources are solved one after another.
+ * The sources run in lockstep: their base directions form one multi-RHS
+ * stack, so every link load of the Dslash serves all of them, and the final
+ * verification / refinement is one batched solve over all (source, shift)
+ * pairs.  The Krylov vectors are FP32 for any sloppy precision other than
+ * FP64, FP64 otherwise; nsrc = 1 is hisq_multishift_cg.
  *   b   device FP64 spinors [nsrc][3][Vh];  x device FP64 [nsrc][nshift][3][Vh]
  *   st  host array of nsrc * nshift stats, [source][shift] (or NULL)
  *   1 <= nsrc <= 64, 1 <= nshift <= 256, nsrc * nshift <= 1024; b and x must

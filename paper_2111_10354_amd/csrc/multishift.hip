@@ -169,41 +169,44 @@ struct MsWorkspace {
     DevBuf t, q, r, p0, pk, part, state, ms, gl, diag, bstack;
 };
 
-// Mixed-precision multi-shift CG for nsrc sources in lockstep.  The Krylov
-// iteration runs with FP32 links and vectors: base residual and direction,
-// every shifted direction and solution; the sources' base directions form one
-// multi-RHS stack, so each link load of the Dslash serves every source.  The
+// Multi-shift CG for nsrc sources in lockstep, its Krylov iteration in
+// precision K (FP32: the mixed form; FP64).  Links and vectors of the
+// iteration (base residual and direction, every shifted direction and
+// solution) are in K; the sources' base directions form one multi-RHS stack,
+// so each link load of the Dslash serves every source.  The
 // base solutions are accumulated in FP64 with reliable updates (x_hi +=
 // x_sloppy, r = b - (A + sigma_0) x_hi in FP64, every ru_period iterations,
 // after a tenfold fall of the iterated residual and at apparent convergence);
 // after such an update the recurrences continue from the recomputed residual,
 // with each shifted residual taken as zeta_k times it.  The shifted residuals
-// are collinear with the base residual only up to the rounding of the FP32
-// operator, so the shifted solutions stall far above the target (the smaller
+// are collinear with the base residual only up to the rounding of the K
+// operator; in FP32 the shifted solutions stall far above the target (the smaller
 // the shift, the higher: between ~1e-3 and ~1e-7 relative for shifts from
 // 1e-4 to 10 in a model of this iteration); the batched mixed-precision CG
 // warm-started from them finishes every (source, shift) on its own FP64 true
 // residual.
 //   b: nsrc FP64 sources [nsrc][spinor];  x: [nsrc][ns][spinor] in the
 //   caller's shift order;  stats: [nsrc][ns] or NULL.
-static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, const int *order,
-                                  const double *shifts, const double *b, double *x,
-                                  const hisq_solver_params &prm, hisq_solver_stats *stats, hipStream_t s) {
+template <int K>
+static int multishift_solve_lockstep(hisq_gauge_s *g, double mass, int m, int ns, const int *order,
+                                     const double *shifts, const double *b, double *x,
+                                     const hisq_solver_params &prm, hisq_solver_stats *stats, hipStream_t s) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     const int vh = g->geom.vh;
-    if (!g->links[F32][0].p) {
-        set_error("multishift: mixed precision needs packed FP32 links in the handle");
+    if (!g->links[K][0].p) {
+        set_error(K == F64 ? "multishift: the handle lacks packed FP64 links"
+                           : "multishift: mixed precision needs packed FP32 links in the handle");
         return HISQ_ERR_UNSUPPORTED;
     }
     const double sig0 = shifts[order[0]];
-    const size_t s64 = spinor_bytes(F64, vh), s32 = spinor_bytes(F32, vh);
+    const size_t s64 = spinor_bytes(F64, vh), sk = spinor_bytes(K, vh);
     const int nb = blas_blocks(vh), nall = m * ns;
     const int nbmax = std::max((vh + 63) / 64, nb);
-    DevBuf r32, t32, q32, p32, x32, x64, t64, ax64, r64, part, state, msb, glb, diag, scal, bstack;
+    DevBuf rk, tk, qk, pk, xk, x64, t64, ax64, r64, part, state, msb, glb, diag, scal, bstack;
     int rc;
-    if ((rc = r32.alloc(s32 * m)) || (rc = t32.alloc(s32 * m)) || (rc = q32.alloc(s32 * m)) ||
-        (rc = p32.alloc(s32 * nall)) || (rc = x32.alloc(s32 * nall)) || (rc = x64.alloc(s64 * nall)) ||
+    if ((rc = rk.alloc(sk * m)) || (rc = tk.alloc(sk * m)) || (rc = qk.alloc(sk * m)) ||
+        (rc = pk.alloc(sk * nall)) || (rc = xk.alloc(sk * nall)) || (rc = x64.alloc(s64 * nall)) ||
         (rc = t64.alloc(s64 * m)) || (rc = ax64.alloc(s64 * m)) || (rc = r64.alloc(s64 * m)) ||
         (rc = part.alloc(sizeof(double) * (size_t)m * nbmax)) || (rc = state.alloc(sizeof(CgState) * m)) ||
         (rc = msb.alloc(sizeof(MsState) * nall)) || (rc = glb.alloc(sizeof(MsGlobal) * m)) ||
@@ -216,9 +219,9 @@ static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, c
     double *pt = (double *)part.p;
     // shift-major stacks: slot k * m + j; the base (k = 0) slots of the
     // direction, sloppy and FP64 solution stacks are the sources' base stacks
-    const Spinor<F32> X = spinor_view<F32>(x32.p, vh), P = spinor_view<F32>(p32.p, vh);
-    const Spinor<F32> Rv = spinor_view<F32>(r32.p, vh);
-    void *p0 = p32.p, *xhi = x64.p;
+    const Spinor<K> X = spinor_view<K>(xk.p, vh), P = spinor_view<K>(pk.p, vh);
+    const Spinor<K> Rv = spinor_view<K>(rk.p, vh);
+    void *p0 = pk.p, *xhi = x64.p;
 
     const std::vector<double> diag0(m, 4.0 * mass * mass + sig0);
     HISQ_HIP_CHECK(hipMemcpyAsync(diag.p, diag0.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
@@ -254,13 +257,13 @@ static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, c
     HISQ_HIP_CHECK(hipMemcpyAsync(gl, hg.data(), sizeof(MsGlobal) * m, hipMemcpyHostToDevice, s));
 
     // r = b, p = p_k = b, x_k = 0, x_hi = 0
-    launch_convert(F64, F32, vh, m, b, r32.p, nullptr, -1, s);
+    launch_convert(F64, K, vh, m, b, rk.p, nullptr, -1, s);
     launch_norm2(vh, m, b, pt, s);
     launch_reduce(RED_INIT, m, pt, nb, base, nullptr, s);
-    launch_zero(F32, vh, nall, x32.p, s);
+    launch_zero(K, vh, nall, xk.p, s);
     launch_zero(F64, vh, m, xhi, s);
     const dim3 rep_grid((vh + 255) / 256, nall);
-    hipLaunchKernelGGL(k_replicate<F32>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), P, m);
+    hipLaunchKernelGGL(k_replicate<K>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh), P, m);
     HISQ_HIP_CHECK(hipGetLastError());
 
     const int tb = 64;
@@ -268,36 +271,36 @@ static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, c
     const dim3 beta_block(std::max(64, std::min(256, ((ns + 63) / 64) * 64)));
     auto iteration = [&](hipStream_t st) -> int {
         int r2;
-        if ((r2 = gauge_dslash(g, 1, F32, F32, F32, m, p0, t32.p, nullptr, nullptr, nullptr, base, st))) return r2;
-        if ((r2 = gauge_dslash(g, 0, F32, F32, F32, m, t32.p, q32.p, p0, (const double *)diag.p, pt, base, st)))
+        if ((r2 = gauge_dslash(g, 1, K, K, K, m, p0, tk.p, nullptr, nullptr, nullptr, base, st))) return r2;
+        if ((r2 = gauge_dslash(g, 0, K, K, K, m, tk.p, qk.p, p0, (const double *)diag.p, pt, base, st)))
             return r2;
-        launch_reduce(RED_ALPHA, m, pt, nb_dslash(g, F32, F32, F32, m, true), base, nullptr, st);
+        launch_reduce(RED_ALPHA, m, pt, nb_dslash(g, K, K, K, m, true), base, nullptr, st);
         hipLaunchKernelGGL(k_ms_alpha, shift_grid, dim3(tb), 0, st, base, ms, gl, ns);
-        launch_update_xr(F32, vh, m, x32.p, r32.p, p0, q32.p, base, pt, st);
+        launch_update_xr(K, vh, m, xk.p, rk.p, p0, qk.p, base, pt, st);
         launch_reduce(RED_BETA, m, pt, nb, base, nullptr, st);
         hipLaunchKernelGGL(k_ms_beta, beta_grid, beta_block, 0, st, base, ms, gl, ns, (int)CG_RUNNING);
-        hipLaunchKernelGGL(k_ms_update<F32>, site_grid, dim3(256), 0, st, X, P, Rv, base, ms, ns, m,
+        hipLaunchKernelGGL(k_ms_update<K>, site_grid, dim3(256), 0, st, X, P, Rv, base, ms, ns, m,
                            (int)CG_RUNNING);
         hipLaunchKernelGGL(k_ms_clear_pending, shift_grid, dim3(tb), 0, st, base, ms, ns, (int)CG_RUNNING);
-        launch_update_p(F32, vh, m, r32.p, p0, base, CG_RUNNING, st);
+        launch_update_p(K, vh, m, rk.p, p0, base, CG_RUNNING, st);
         return (int)(hipGetLastError() == hipSuccess ? HISQ_OK : HISQ_ERR_HIP);
     };
     // FP64 reliable update of the base systems flagged CG_ATTENTION
     auto reliable = [&]() -> int {
         int r2;
-        launch_accum_zero(F32, vh, m, xhi, x32.p, base, CG_ATTENTION, s);
+        launch_accum_zero(K, vh, m, xhi, xk.p, base, CG_ATTENTION, s);
         if ((r2 = gauge_dslash(g, 1, F64, F64, F64, m, xhi, t64.p, nullptr, nullptr, nullptr, nullptr, s))) return r2;
         if ((r2 = gauge_dslash(g, 0, F64, F64, F64, m, t64.p, ax64.p, xhi, (const double *)diag.p, pt, nullptr, s)))
             return r2;
         launch_residual(vh, m, b, ax64.p, r64.p, base, CG_ATTENTION, pt, s);
         launch_reduce(RED_TRUE, m, pt, nb, base, nullptr, s);
-        launch_convert(F64, F32, vh, m, r64.p, r32.p, base, CG_RESUME, s);
+        launch_convert(F64, K, vh, m, r64.p, rk.p, base, CG_RESUME, s);
         // the shifts' beta and direction updates of this iteration, from the new residual
         hipLaunchKernelGGL(k_ms_beta, beta_grid, beta_block, 0, s, base, ms, gl, ns, (int)CG_RESUME);
-        hipLaunchKernelGGL(k_ms_update<F32>, site_grid, dim3(256), 0, s, X, P, Rv, base, ms, ns, m,
+        hipLaunchKernelGGL(k_ms_update<K>, site_grid, dim3(256), 0, s, X, P, Rv, base, ms, ns, m,
                            (int)CG_RESUME);
         hipLaunchKernelGGL(k_ms_clear_pending, shift_grid, dim3(tb), 0, s, base, ms, ns, (int)CG_RESUME);
-        launch_update_p(F32, vh, m, r32.p, p0, base, CG_RESUME, s);
+        launch_update_p(K, vh, m, rk.p, p0, base, CG_RESUME, s);
         launch_resume_flags(m, base, s);
         return (int)(hipGetLastError() == hipSuccess ? HISQ_OK : HISQ_ERR_HIP);
     };
@@ -345,11 +348,11 @@ static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, c
     HISQ_HIP_CHECK(hipMemcpyAsync(hb.data(), base, sizeof(CgState) * m, hipMemcpyDeviceToHost, s));
     HISQ_HIP_CHECK(hipStreamSynchronize(s));
     // a breakdown or a stop at the cap leaves a base's sloppy part unfolded
-    for (int f : {(int)CG_BREAKDOWN, (int)CG_MAXITER}) launch_accum_zero(F32, vh, m, xhi, x32.p, base, f, s);
-    hipLaunchKernelGGL(k_ms_flush<F32>, site_grid, dim3(256), 0, s, X, P, ms, ns, m);
+    for (int f : {(int)CG_BREAKDOWN, (int)CG_MAXITER}) launch_accum_zero(K, vh, m, xhi, xk.p, base, f, s);
+    hipLaunchKernelGGL(k_ms_flush<K>, site_grid, dim3(256), 0, s, X, P, ms, ns, m);
     HISQ_HIP_CHECK(hipMemcpyAsync(hm.data(), ms, sizeof(MsState) * nall, hipMemcpyDeviceToHost, s));
     if (ns > 1)
-        launch_convert(F32, F64, vh, nall - m, (char *)x32.p + s32 * m, (char *)x64.p + s64 * m, nullptr, -1, s);
+        launch_convert(K, F64, vh, nall - m, (char *)xk.p + sk * m, (char *)x64.p + s64 * m, nullptr, -1, s);
 
     // every (source, shift) finished on its FP64 true residual by the batched mixed CG
     static const bool trace = std::getenv("HISQ_SOLVER_TRACE") != nullptr;
@@ -360,8 +363,8 @@ static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, c
             it = std::max(it, cj.iter);
             ru += cj.reliable;
         }
-        std::fprintf(stderr, "[multishift] mixed: %d source(s) x %d shifts, %d base iterations, %d reliable updates, %.3f s\n",
-                     m, ns, it, ru, std::chrono::duration<double>(clk::now() - t0).count());
+        std::fprintf(stderr, "[multishift] %s: %d source(s) x %d shifts, %d base iterations, %d reliable updates, %.3f s\n",
+                     K == F64 ? "FP64 lockstep" : "mixed", m, ns, it, ru, std::chrono::duration<double>(clk::now() - t0).count());
     }
     hipLaunchKernelGGL(k_replicate<F64>, rep_grid, dim3(256), 0, s, spinor_view<F64>((void *)b, vh),
                        spinor_view<F64>(bstack.p, vh), m);
@@ -386,8 +389,8 @@ static int multishift_solve_mixed(hisq_gauge_s *g, double mass, int m, int ns, c
         std::fprintf(stderr, "[multishift] refinement: at most %d iterations, total %.3f s\n", most, total_ms / 1e3);
     }
     if (stats) {
-        const double per_iter = (double)(dslash_algorithmic_bytes(F32, F32, F32, vh, m, false, g->comp_mode) +
-                                         dslash_algorithmic_bytes(F32, F32, F32, vh, m, true, g->comp_mode));
+        const double per_iter = (double)(dslash_algorithmic_bytes(K, K, K, vh, m, false, g->comp_mode) +
+                                         dslash_algorithmic_bytes(K, K, K, vh, m, true, g->comp_mode));
         const double per_ru = (double)(dslash_algorithmic_bytes(F64, F64, F64, vh, 1, false, g->comp_mode) +
                                        dslash_algorithmic_bytes(F64, F64, F64, vh, 1, true, g->comp_mode));
         for (int j = 0; j < m; ++j)
@@ -420,7 +423,7 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     for (int k = 0; k < ns; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return shifts[a] < shifts[c]; });
     if (prm.sloppy_prec != HISQ_PREC_FP64)
-        return multishift_solve_mixed(g, mass, 1, ns, order.data(), shifts, b, x, prm, stats, s);
+        return multishift_solve_lockstep<F32>(g, mass, 1, ns, order.data(), shifts, b, x, prm, stats, s);
     const double sig0 = shifts[order[0]];
 
     const size_t s64 = spinor_bytes(F64, vh);
@@ -568,26 +571,19 @@ int multishift_solve(hisq_gauge_s *g, double mass, int ns, const double *shifts,
     return worst;
 }
 
-// nsrc sources, each with every shift: the mixed form runs them in lockstep;
-// the FP64 form solves one source after another.
+// nsrc sources, each with every shift, run in lockstep (one source: the
+// single-source solver).  With FP64 sloppy precision the Krylov vectors are
+// FP64 as well; the reliable updates then only re-anchor the iterated residual
+// on the true one every ru_period iterations.
 int multishift_solve_batched(hisq_gauge_s *g, double mass, int nsrc, int ns, const double *shifts, const double *b,
                              double *x, const hisq_solver_params &prm, hisq_solver_stats *stats, hipStream_t s) {
-    const size_t s64 = spinor_bytes(F64, g->geom.vh);
-    if (prm.sloppy_prec != HISQ_PREC_FP64) {
-        std::vector<int> order(ns);
-        for (int k = 0; k < ns; ++k) order[k] = k;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return shifts[a] < shifts[c]; });
-        return multishift_solve_mixed(g, mass, nsrc, ns, order.data(), shifts, b, x, prm, stats, s);
-    }
-    int worst = HISQ_OK;
-    for (int j = 0; j < nsrc; ++j) {
-        const int rc = multishift_solve(g, mass, ns, shifts, (const double *)((const char *)b + s64 * j),
-                                        (double *)((char *)x + s64 * (size_t)j * ns), prm,
-                                        stats ? stats + (size_t)j * ns : nullptr, s);
-        if (rc < 0) return rc;
-        if (status_severity(rc) > status_severity(worst)) worst = rc;
-    }
-    return worst;
+    if (nsrc == 1) return multishift_solve(g, mass, ns, shifts, b, x, prm, stats, s);
+    std::vector<int> order(ns);
+    for (int k = 0; k < ns; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return shifts[a] < shifts[c]; });
+    if (prm.sloppy_prec != HISQ_PREC_FP64)
+        return multishift_solve_lockstep<F32>(g, mass, nsrc, ns, order.data(), shifts, b, x, prm, stats, s);
+    return multishift_solve_lockstep<F64>(g, mass, nsrc, ns, order.data(), shifts, b, x, prm, stats, s);
 }
 
 }  // namespace hisq

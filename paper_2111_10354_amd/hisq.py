@@ -296,8 +296,9 @@ def multishift_cg(g: Gauge, mass: float, shifts, b, x, params: SolverParams | No
 
 def multishift_cg_batched(g: Gauge, mass: float, nsrc: int, shifts, b, x, params: SolverParams | None = None,
                           stream=None):
-    """nsrc sources b [nsrc][spinor] with the same shifts; x [nsrc][nshift][spinor].
-    Returns (status, [stats per (source, shift)], source-major)."""
+    """nsrc sources b [nsrc][spinor] with the same shifts, solved in lockstep;
+    x [nsrc][nshift][spinor].  Returns (status, [stats per (source, shift)],
+    source-major)."""
     n, m = len(shifts), int(nsrc)
     sb = spinor_bytes("fp64", g.vh)
     _need(b, sb * m, "b")

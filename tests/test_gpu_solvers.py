@@ -269,8 +269,9 @@ def _ms_batched(g, dims, mass, srcs, shifts, **kw):
 
 @pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
 def test_multishift_batched(c1, sloppy):
-    """Three sources sharing four (unsorted) shifts in one call; the mixed
-    form iterates them in lockstep through the three-RHS Dslash.  Every
+    """Three sources sharing four (unsorted) shifts in one call, iterated in
+    lockstep through the three-RHS Dslash (FP64, or FP32 Krylov vectors in the
+    mixed forms).  Every
     (source, shift) solution meets the tolerance on the oracle's operator, in
     the caller's [source][shift] order, with its own stats.  The sources
     differ in norm by 1e3, so a stopping rule shared between them would leave
