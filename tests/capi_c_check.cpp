@@ -1,6 +1,6 @@
 // The C ABI from a plain host program, without Python or torch: device
 // memory from the HIP runtime, the entry points of include/hisq.h, and the C
-// oracle (oracle/hisq_oracle.c) as the judge.  On an 8^4 lattice with random
+// oracle (oracle/hisq_oracle.c) as the arbiter.  On an 8^4 lattice with random
 // (non-unitary) fat and Naik links it checks
 //  * hisq_dslash_eo (FP64, both output parities) against oracle_dslash;
 //  * hisq_dslash_multi_rhs with the (A + sigma_i) epilogue (FP64, 3 RHS)

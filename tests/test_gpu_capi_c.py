@@ -1,6 +1,6 @@
 """The C ABI from a plain host program (tests/capi_c_check.cpp, built by
 __graft_entry__.build()): HIP runtime allocations, the entry points of
-include/hisq.h, no Python or torch in the loop, and the C oracle as the judge
+include/hisq.h, no Python or torch in the loop, and the C oracle as the arbiter
 (Dslash both parities, the multi-RHS epilogue, batched plain and mixed CG,
 FP64 and mixed multi-shift, error paths)."""
 
