@@ -267,8 +267,8 @@ def _ms_batched(g, dims, mass, srcs, shifts, **kw):
     return rc, st, sol
 
 
-@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
-def test_multishift_batched(c1, sloppy):
+@pytest.mark.parametrize("sloppy,graph_chunk", [("fp64", 16), ("fp32", 16), ("fp16s", 16), ("fp64", 0), ("fp32", 0)])
+def test_multishift_batched(c1, sloppy, graph_chunk):
     """Three sources sharing four (unsorted) shifts in one call, iterated in
     lockstep through the three-RHS Dslash (FP64, or FP32 Krylov vectors in the
     mixed forms).  Every
@@ -281,8 +281,8 @@ def test_multishift_batched(c1, sloppy):
     shifts = [0.3, 0.0, 0.01, 0.08]
     srcs = synth.gaussian_source(dims, 4, 3, parity=0, index0=80)
     srcs[1] = 1e-3 * srcs[1]
-    flush(f"batched multishift 8^4 3 sources x 4 shifts {sloppy}")
-    rc, st, sol = _ms_batched(g, dims, mass, srcs, shifts, sloppy_prec=sloppy)
+    flush(f"batched multishift 8^4 3 sources x 4 shifts {sloppy} chunk={graph_chunk}")
+    rc, st, sol = _ms_batched(g, dims, mass, srcs, shifts, sloppy_prec=sloppy, graph_chunk=graph_chunk)
     assert rc == 0, st
     assert len(st) == 12
     for j in range(3):
