@@ -217,7 +217,7 @@ def main():
         fl = generate_fields(("c3",), dims)
         import torch
         from paper_2111_10354_amd import hisq
-        out, _ = run_c3_solvers(hisq, torch, tune, fl["c3"], batched_fp64=True)
+        out, _ = run_c3_solvers(hisq, torch, tune, fl["c3"], extended=True)
         print(json.dumps(out), flush=True)
         return
     if args.c2_dslash:
@@ -652,20 +652,23 @@ def run_mrhs_only(args, dims, tune):
     g.close()
 
 
-def run_c3_solvers(hisq, torch, tune, fields, batched_fp64=False):
+def run_c3_solvers(hisq, torch, tune, fields, extended=False):
     """48^3 x 12, m = 0.005: one RHS by plain FP64 CG and by mixed FP32 CG, all
     16 RHS batched through the multi-RHS Dslash (mixed FP32, FP64 reliable
     updates), the 12-shift ladder sigma_k = 10^(-4 + 4k/11) by multi-shift CG,
     and the two-flavour pseudofermion heat bath phi = A^(1/4) eta (16 Remez
-    poles) and action phi^+ A^(-1/2) phi (16 Zolotarev poles); every solve to
-    the 1e-10 FP64 true residual."""
+    poles) and action phi^+ A^(-1/2) phi (16 Zolotarev poles), and the heat
+    bath of four sources in one batched call; every solve to the 1e-10 FP64
+    true residual.  `extended` adds the FP64 four-source heat bath and the
+    mixed forms with FP16S-sloppy refinement."""
     import synth
     c = synth.CONFIGS["c3"]
     dims, mass, n, ns = c["dims"], c["mass"], c["nrhs"], c["nshift"]
     vh = synth.volume(dims) // 2
     F, L = fields
-    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), ("fp64", "fp32"))
-    for p in ("fp64", "fp32"):
+    precs = ("fp64", "fp32", "fp16s") if extended else ("fp64", "fp32")
+    g = hisq.Gauge(dims, torch.from_numpy(F).cuda(), torch.from_numpy(L).cuda(), precs)
+    for p in precs:
         for k in (1, 4, n, ns):
             hisq.autotune(g, p, k, tune)
     items = []
@@ -738,8 +741,12 @@ def run_c3_solvers(hisq, torch, tune, fields, batched_fp64=False):
     a0, al, sh, delta = hisq.zolotarev_inv_sqrt(lo, 1.05 * hi, npole)
     eta2 = float(torch.dot(b0.view(torch.float64), b0.view(torch.float64)))
     phi_one = {}
-    for sl in ("fp64", "fp32"):
-        sfx = "" if sl == "fp64" else "_mixed_fp32"
+    # the extended (--c3-solvers) run adds the mixed form with FP16S-sloppy
+    # refinement (FP32 Krylov iteration as before)
+    hb_precs = ("fp64", "fp32", "fp16s") if extended else ("fp64", "fp32")
+    sfx_of = {"fp64": "", "fp32": "_mixed_fp32", "fp16s": "_mixed_fp16s"}
+    for sl in hb_precs:
+        sfx = sfx_of[sl]
         prm = hisq.solver_params(sloppy_prec=sl)
         warm = hisq.solver_params(sloppy_prec=sl, max_iter=50)
         phi = torch.empty_like(b0)
@@ -770,10 +777,10 @@ def run_c3_solvers(hisq, torch, tune, fields, batched_fp64=False):
     # systems in one batched CG
     nps = 4
     bq = b[:nps * sb]
-    # (the FP64 form only in the --c3-solvers run: the default run keeps its
-    # total time well inside a few minutes)
-    for sl in (("fp64", "fp32") if batched_fp64 else ("fp32",)):
-        sfx = "" if sl == "fp64" else "_mixed_fp32"
+    # (the FP64 and FP16S-refinement forms only in the --c3-solvers run: the
+    # default run keeps its total time well inside a few minutes)
+    for sl in (hb_precs if extended else ("fp32",)):
+        sfx = sfx_of[sl]
         phis = torch.empty_like(bq)
         prm = hisq.solver_params(sloppy_prec=sl)
         (rc, st), wall = timed(
