@@ -236,9 +236,13 @@ def test_binding_rejects_undersized_buffers_before_any_call():
         lambda: hisq.rational_apply(g, 0.1, 1.0, [1.0], [0.1], one32, one64),
         lambda: hisq.precond_apply(g, None, one32[:-8], one32),
         lambda: hisq.gauge_set_thin(g, one64),
+        lambda: hisq.multishift_cg_batched(g, 0.1, 2, [0.0, 0.1], one64, one64),   # b holds one of two sources
+        lambda: hisq.multishift_cg_batched(g, 0.1, 1, [0.0, 0.1], one64, one64),   # x holds one of two shifts
+        lambda: hisq.rational_apply_batched(g, 0.1, 2, 1.0, [1.0], [0.1], one64, one64),
     ]
+    # CPU tensors: the size check must fire before the device check would
     for i, call in enumerate(calls):
-        with pytest.raises(ValueError):
+        with pytest.raises(ValueError, match="the call touches"):
             call()
 
 
