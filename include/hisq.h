@@ -87,8 +87,9 @@ typedef struct hisq_nn_s *hisq_nn_t;
 
 /* Library version (major*10000 + minor*100 + patch); equals HISQ_VERSION of
  * the header the library was built with.  0.2.0: hisq_solver_params gained
- * ru_delta (callers built against 0.1 pass a shorter struct). */
-#define HISQ_VERSION 200
+ * ru_delta (callers built against 0.1 pass a shorter struct).  0.3.0:
+ * hisq_multishift_cg_batched and hisq_rational_apply_batched. */
+#define HISQ_VERSION 300
 int hisq_version(void);
 
 /* Message describing the calling thread's most recent error ("" if none). */

@@ -139,7 +139,7 @@ def test_heatbath_action_identity(cuda_device, flavour):
     g.close()
 
 
-@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16s"])
 def test_batched_sources_match_oracle(cuda_device, sloppy):
     """Four pseudofermion sources through one batched call: each equals the
     oracle's partial-fraction sum to 1e-8, in the caller's order."""
