@@ -430,6 +430,34 @@ def main():
             if cg is not None:
                 cpu["cg_32x32x32x8"]["extrapolated_seconds_to_solution"] = per_it * cg["plain_fp64"]["iterations"]
             log(f"oracle CG 32^3x8: {1e3 * per_it:.1f} ms per iteration ({it2} timed)")
+        # the oracle's whole plain CG on the 8^4 workload (seconds), one A
+        # application on the benchmark lattice, and per-iteration time on 48^3 x 12
+        c1 = synth.CONFIGS["c1"]
+        F1, L1 = synth.hisq_links(c1["dims"], synth.CFG_IDS["c1"], c1["eps"])
+        b1 = synth.gaussian_source(c1["dims"], synth.CFG_IDS["c1"], 1, parity=0)[0]
+        t1 = time.time()
+        _, st1, it1, tr1 = oracle.cg(c1["dims"], F1, L1, c1["mass"], b1, tol=1e-10)
+        cpu["cg_8x8x8x8"] = {"seconds_to_solution": time.time() - t1, "iterations": it1, "status": st1,
+                             "true_residual": tr1}
+        log(f"oracle CG 8^4: {cpu['cg_8x8x8x8']['seconds_to_solution']:.3f} s, {it1} iterations")
+        ev = synth.gaussian_source(dims, synth.CFG_IDS["c5"], 1, parity=0)[0]
+        t1 = time.time()
+        oracle.normal_op(dims, F, L, cfg["mass"], ev)
+        cpu["normal_op_seconds"] = time.time() - t1
+        del ev
+        log(f"oracle A application on {dims}: {cpu['normal_op_seconds']:.2f} s")
+        if "c3" in fields and c3 is not None:
+            c3c = synth.CONFIGS["c3"]
+            F3, L3 = fields["c3"]
+            b3 = synth.gaussian_source(c3c["dims"], synth.CFG_IDS["c3"], 1, parity=0)[0]
+            t1 = time.time()
+            _, _, it3, _ = oracle.cg(c3c["dims"], F3, L3, c3c["mass"], b3, tol=1e-10, max_iter=30)
+            per3 = (time.time() - t1) / max(it3, 1)
+            cpu["cg_48x48x48x12"] = {
+                "seconds_per_iteration": per3, "iterations_timed": it3,
+                "extrapolated_seconds_to_solution": per3 * c3["plain_fp64_1rhs"]["iterations_max"],
+                "note": "plain FP64 CG of the oracle; x the GPU's plain-CG iteration count (extrapolated)"}
+            log(f"oracle CG 48^3x12: {1e3 * per3:.1f} ms per iteration ({it3} timed)")
         # the oracle's true residual of every solution of the run
         residuals = {}
         t1 = time.time()
