@@ -7,7 +7,7 @@
 //    against oracle_normal_op;
 //  * hisq_cg_solve (plain FP64 and mixed FP32, 2 RHS) and hisq_multishift_cg
 //    (FP64 and mixed, 3 shifts) on the oracle's true residual, and
-//    hisq_multishift_cg_batched (mixed, 2 sources x 2 shifts);
+//    hisq_multishift_cg_batched (FP64 and mixed, 2 sources x 2 shifts);
 //  * that bad arguments return HISQ_ERR_INVALID with a message.
 // Prints one line per check and exits non-zero on the first failure.
 #include <hip/hip_runtime_api.h>
@@ -225,8 +225,9 @@ int main() {
         }
     }
 
-    // two sources with the same shifts in one call (mixed: lockstep through the 2-RHS Dslash)
-    {
+    // two sources with the same shifts in one call, in lockstep through the
+    // 2-RHS Dslash (FP32 Krylov vectors in the mixed form, FP64 otherwise)
+    for (int sloppy : {HISQ_PREC_FP32, HISQ_PREC_FP64}) {
         const int ns = 2, m = 2;
         const double shifts[ns] = {0.05, 0.0};
         std::vector<std::vector<double>> bs;
@@ -240,11 +241,11 @@ int main() {
         HIP(hipMemcpy(db.p, stack.data(), m * sb, hipMemcpyHostToDevice));
         hisq_solver_params prm;
         hisq_solver_params_default(&prm);
-        prm.sloppy_prec = HISQ_PREC_FP32;
+        prm.sloppy_prec = sloppy;
         hisq_solver_stats st[m * ns];
         rc = hisq_multishift_cg_batched(g, mass, m, ns, shifts, (const double *)db.p, (double *)dx.p, &prm, st,
                                         nullptr);
-        CHECK(rc == HISQ_OK, "batched multishift: %d %s", rc, hisq_last_error());
+        CHECK(rc == HISQ_OK, "batched multishift sloppy %d: %d %s", sloppy, rc, hisq_last_error());
         std::vector<double> xs(m * ns * 6 * VH);
         HIP(hipMemcpy(xs.data(), dx.p, m * ns * sb, hipMemcpyDeviceToHost));
         for (int j = 0; j < m; ++j)
@@ -253,7 +254,8 @@ int main() {
                 std::vector<double> xk(xs.begin() + at, xs.begin() + at + 6 * VH);
                 const double res = oracle_true_residual(L, fat.data(), lng.data(), mass, shifts[k], bs[j].data(),
                                                         from_parity(xk, 0).data());
-                std::printf("batched multishift source %d shift %g: oracle true residual %.2e\n", j, shifts[k], res);
+                std::printf("batched multishift sloppy %d source %d shift %g: oracle true residual %.2e\n", sloppy, j,
+                            shifts[k], res);
                 CHECK(res <= 1e-10 && st[j * ns + k].status == HISQ_OK, "batched multishift %d %d: %.3e", j, k, res);
             }
         rc = hisq_multishift_cg_batched(g, mass, 0, ns, shifts, (const double *)db.p, (double *)dx.p, &prm, st,
