@@ -326,6 +326,10 @@ int hisq_multishift_cg(hisq_gauge_t g, double mass, int nshift, const double *sh
  *   st  host array of nsrc * nshift stats, [source][shift] (or NULL)
  *   1 <= nsrc <= 64, 1 <= nshift <= 256, nsrc * nshift <= 1024; b and x must
  *   not overlap.  Returns the worst status over all (source, shift) pairs.
+ * Workspace (allocated by the call): nsrc * nshift * (2 FP64 + 2 Krylov-
+ * precision) spinors for the iteration, a few per source, and the vectors of
+ * the refinement's batched CG on top; HISQ_ERR_OOM if the device cannot hold
+ * them (at 96^3 x 24 an FP64 spinor is 510 MB).
  */
 int hisq_multishift_cg_batched(hisq_gauge_t g, double mass, int nsrc, int nshift,
                                const double *shifts, const double *b, double *x,
